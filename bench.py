@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Benchmark: words sorted per second (bit-exact), batched vs per-bucket launch.
+
+Default workload: the batching workload -- 4,096 independent word lists with
+sizes log-uniform in [16, 65,536] (~31.8 M words), each drawn like the small
+single-list workload (800-word seeded vocabulary, lengths 1-12, Zipf 1.1,
+5% capitalised).  A step sorts the whole batch: bucketize, key pack, tile
+odd-even transposition sort and block merge-split, all lists in one captured
+graph launch.  Inputs are device-resident before timing starts.
+
+Prints one JSON line.  See the design doc for the roofline definitions.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import wordgen  # noqa: E402
+
+PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12     # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T ops/s
+PEAK_HBM_GBS = 8000.0
+
+
+def kmax_for(D):
+    return 64 if D <= 2 else 32 if D <= 4 else 16 if D <= 8 else 8 if D <= 16 else 4
+
+
+def tile_for(D, want):
+    return min(want, 64 * kmax_for(D))
+
+
+def workload_structure(offsets, req_start, max_len, tile_keys):
+    """Host-side census of the work the method does on this input: per record
+    width D the odd-even transposition tiles and their compare-exchanges, and
+    the merge-split pairs and bytes.  Computed from word lengths only."""
+    lens = np.diff(offsets)
+    R = len(req_start) - 1
+    rid = np.repeat(np.arange(R), np.diff(req_start))
+    ml1 = max_len + 1
+    counts = np.bincount(rid * ml1 + lens, minlength=R * ml1).reshape(R, ml1)
+    out = {}
+    merge_pairs = 0
+    merge_bytes = 0
+    phases_max = 0
+    for L in range(1, ml1):
+        D = (L + 3) // 4 + 1
+        W = (L + 7) // 8
+        T = tile_for(D, tile_keys)
+        n = counts[:, L].astype(np.int64)
+        n = n[n >= 2]
+        if len(n) == 0:
+            continue
+        full = n // T
+        rest = n - full * T
+        ce = full * (T * (T - 1) // 2) + rest * (rest - 1) // 2
+        ntiles = full + (rest > 0)
+        d = out.setdefault(D, {"tiles": 0, "ce": 0, "words": 0})
+        d["tiles"] += int(ntiles.sum())
+        d["ce"] += int(ce.sum())
+        d["words"] += int(n.sum())
+        for p, nb in zip(ntiles, n):
+            if p < 2:
+                continue
+            phases_max = max(phases_max, int(p))
+            rec = 8 * W + 4
+            for s in range(p):
+                for a in range(s & 1, p - 1, 2):
+                    tot = T + min(T, int(nb) - (a + 1) * T)
+                    merge_pairs += 1
+                    merge_bytes += 2 * tot * rec
+    return out, merge_pairs, merge_bytes, phases_max
+
+
+def cpu_info():
+    n = len(os.sched_getaffinity(0))
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, model
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tile", type=int, default=0, help="tile_keys (0: autotune cache or default)")
+    ap.add_argument("--merge-threads", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-bucket launch form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=8,
+                    help="CPU baseline samples every k-th list of the batch")
+    ap.add_argument("--json-out", default="")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by list across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    # inputs first (spawned worker processes, before the GPU is opened)
+    t0 = time.time()
+    batch = wordgen.batch()
+    gen_s = time.time() - t0
+    max_len = 12
+    total = batch.total
+
+    import torch
+    import paper_1407_6603_amd as bs
+    from paper_1407_6603_amd import autotune
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    tile, mthreads, tuned_from = args.tile, args.merge_threads, "flags"
+    if tile == 0 and mthreads == 0:
+        tile, mthreads, tuned_from = autotune.lookup(torch.cuda.get_device_name(0), "batch4096")
+
+    b_t, o_t = bs.to_device(batch.bytes, batch.offsets, dev)
+    rs_t = torch.from_numpy(batch.req_start).to(dev)
+    perm = torch.empty(total, dtype=torch.int32, device=dev)
+    cap_req = int(np.diff(batch.req_start).max())
+    tune = bs.tuning(tile, mthreads, bs.FLAG_STAGE_EVENTS)
+    plan = bs.Plan(total, batch.R, cap_req, max_len, tune)
+    ws = bs.Workspace(plan.workspace_bytes, dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.execute(b_t, o_t, rs_t, batch.req_start, ws, out=perm)
+    torch.cuda.synchronize()
+    bs.check_device_status(ws)
+
+    # ---- timed region: K steps, per-step events, per-stage events in the graph
+    stage_sum = {}
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.execute(b_t, o_t, rs_t, batch.req_start, ws, out=perm)
+        for k, v in plan.stage_ms().items():     # waits for this step
+            stage_sum[k] = stage_sum.get(k, 0.0) + v
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / args.steps
+    stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
+    value = total / (ms_per_step / 1e3)
+    bs.check_device_status(ws)
+    got = perm.cpu().numpy()
+
+    # ---- the plain form: one launch per (list, length) sub-array and per phase
+    plain = None
+    if not args.no_plain:
+        ptune = bs.tuning(tile, mthreads, bs.FLAG_PER_BUCKET_LAUNCH)
+        pws = bs.Workspace(bs.workspace_bytes(total, max_len, batch.R), dev)
+        pperm = torch.empty(total, dtype=torch.int32, device=dev)
+        bs.sort_batch(b_t, o_t, rs_t, batch.req_start, max_len, ptune, pws, out=pperm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bs.sort_batch(b_t, o_t, rs_t, batch.req_start, max_len, ptune, pws, out=pperm)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - t1
+        bs.check_device_status(pws)
+        same = bool(np.array_equal(pperm.cpu().numpy(), got))
+        plain = {"value": total / plain_s, "unit": "words/s", "ms_per_step": plain_s * 1e3,
+                 "identical_to_batched": same}
+        del pws, pperm
+
+    # ---- roofline of the dominant kernel
+    struct, merge_pairs, merge_bytes, phases_max = workload_structure(
+        batch.offsets, batch.req_start, max_len, tile or 1024)
+    oets = {k: v for k, v in stage_ms.items() if k.startswith("oets_d")}
+    dom = max(stage_ms, key=stage_ms.get)
+    roof = None
+    if dom.startswith("oets_d"):
+        D = int(dom[len("oets_d"):])
+        ce = struct[D]["ce"]
+        ops = 3 * D * ce                       # D dword compares + 2D dword selects per CE
+        achieved = ops / (stage_ms[dom] / 1e3) / 1e12
+        roof = {"bound": "alu", "kernel": f"k_oets_tiles<{D}>", "achieved": achieved,
+                "peak": PEAK_INT32_TOPS, "unit": "TOP/s", "frac": achieved / PEAK_INT32_TOPS,
+                "traffic": None, "ce_per_launch": ce,
+                "ce_per_s": ce / (stage_ms[dom] / 1e3), "ops_per_ce": 3 * D}
+    elif dom == "merge_split":
+        achieved = merge_bytes / (stage_ms[dom] / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": "k_merge_phase", "achieved": achieved,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                "traffic": None, "bytes_per_step": merge_bytes}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": None, "traffic": None}
+
+    # ---- CPU baseline: the oracle (paper's procedure) on a strided sample
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ncores, model = cpu_info()
+        idx = list(range(0, batch.R, args.cpu_stride))
+        sub = wordgen.Batch.concat([batch.request(r) for r in idx])
+        t2 = time.perf_counter()
+        operm, ncmp = oracle.bubble_sort_batch(sub.bytes, sub.offsets, sub.req_start, max_len,
+                                               threads=ncores)
+        cpu_s = time.perf_counter() - t2
+        cpu = {"value": sub.total / cpu_s, "unit": "words/s", "cores": ncores, "kind": "oracle",
+               "cpu_model": model, "seconds": cpu_s, "comparisons": ncmp,
+               "sample": f"every {args.cpu_stride}th list of the 4,096 ({len(idx)} lists, "
+                         f"{sub.total} words); bucket-then-bubble procedure, one list per "
+                         f"thread, {ncores} threads"}
+        gsub = np.concatenate([got[batch.req_start[r]:batch.req_start[r + 1]] for r in idx])
+        parity = {"lists_checked": len(idx), "words_checked": sub.total,
+                  "bit_exact": bool(np.array_equal(gsub, operm))}
+
+    line = {
+        "metric": "words sorted/sec (bit-exact), batched graph launch",
+        "value": value, "unit": "words/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "batch-4096: 4,096 lists, sizes log-uniform in [16, 65536], "
+                               f"{total} words, lengths 1-12, Zipf 1.1 over an 800-word "
+                               "vocabulary per list, 5% capitalised",
+                   "global_batch": batch.R, "words": total, "max_len": max_len,
+                   "tile_keys": tile or 1024, "merge_threads": mthreads or 256,
+                   "tuning_source": tuned_from, "parallelism": "single GPU"},
+        "per_bucket_launch": plain,
+        "batched_over_per_bucket": (value / plain["value"]) if plain else None,
+        "stage_ms": stage_ms,
+        "merge_phases_max": phases_max,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "gpu": torch.cuda.get_device_name(0),
+        "gen_seconds": gen_s,
+    }
+    s = json.dumps(line)
+    print(s, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(s + "\n")
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * bsort -- length-bucketed odd-even transposition sort of words on AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operation (Alyasseri et al., "Parallelize Bubble Sort Algorithm Using
+ * OpenMP", Section II pre-processing phases 2-3 and Section III approach one
+ * step 4): words are distributed into sub-arrays by their number of
+ * characters, shorter words before longer ones, and each sub-array is sorted
+ * by the ASCII codes of its words' letters.  The paper sorts each sub-array
+ * with bubble sort; this library runs bubble sort's data-parallel form,
+ * odd-even transposition sort, on tiles of a sub-array, and joins tiles with
+ * a block odd-even merge-split.  The result is exact and unique:
+ *
+ *   perm[k] = index of the k-th word in increasing (length, bytes, index)
+ *             order, bytes compared as unsigned 8-bit values (memcmp order),
+ *             ties (equal words) in increasing input index.
+ *
+ * Conventions for every entry point
+ *   - Words are given as one byte buffer with no separators plus int64
+ *     offsets: word i is bytes[offsets[i] .. offsets[i+1]-1].
+ *   - Every array argument named "device" is device memory on the current
+ *     HIP device, allocated and owned by the caller; the library never frees
+ *     or keeps it beyond the call's stream work.  Arrays named "host" are
+ *     host memory read during the call only.
+ *   - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *     void*; NULL is the null stream) unless stated otherwise.  Outputs are
+ *     valid once the stream reaches the call's work.
+ *   - No entry point allocates device memory except bsort_plan_create.
+ *     Scratch space is a caller-allocated workspace of at least
+ *     bsort_workspace_bytes(...) bytes, 256-byte aligned.  Calls that run
+ *     concurrently must use distinct workspaces.
+ *   - Host-side argument checks return a status synchronously and launch
+ *     nothing when they fail.  Faults found on the device (a word longer than
+ *     max_len, offsets that decrease or point past n_bytes, request bounds
+ *     that decrease) set a status word in the workspace, read back by
+ *     bsort_get_device_status; the affected words are left out of the
+ *     result, and outputs are then unspecified but stay inside their
+ *     arrays.  No entry point aborts or throws.
+ *   - n_words == 0 is allowed and does nothing.
+ */
+#ifndef BSORT_H
+#define BSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Longest word accepted.  Keys are ceil(L/8) uint64 lanes, so at most 8. */
+#define BSORT_MAX_LEN 64
+
+typedef enum {
+    BSORT_OK = 0,
+    BSORT_E_INVALID = 1,     /* bad argument: null pointer, negative size, bad offsets */
+    BSORT_E_TOO_LONG = 2,    /* max_len > BSORT_MAX_LEN, or a word longer than max_len */
+    BSORT_E_NO_MEMORY = 3,   /* an allocation failed (plans only) */
+    BSORT_E_WORKSPACE = 4,   /* workspace too small or misaligned */
+    BSORT_E_HIP = 5,         /* a HIP runtime call failed; see bsort_last_error */
+    BSORT_E_CAPACITY = 6     /* batch exceeds the capacity a plan was built for */
+} bsort_status;
+
+typedef void *bsort_stream_t;   /* hipStream_t */
+
+/* One list of words (one request). */
+typedef struct {
+    const uint8_t *bytes;    /* device [n_bytes] concatenated word bytes */
+    int64_t n_bytes;         /* size of bytes; every offset must be <= n_bytes */
+    const int64_t *offsets;  /* device [n_words+1], non-decreasing, offsets[0] >= 0 */
+    int32_t n_words;         /* 0 <= n_words < 2^31 */
+    int32_t max_len;         /* bound on word length, 0 <= max_len <= BSORT_MAX_LEN */
+} bsort_words;
+
+/* Sub-arrays by length (the paper's count array and sub-arrays). */
+typedef struct {
+    int32_t *counts;         /* device [max_len+1]: counts[L] = words of length L */
+    int32_t *starts;         /* device [max_len+2]: exclusive running sum of counts */
+    int32_t *order;          /* device [n_words]: word indices grouped by length,
+                                shortest first, input order inside each length */
+} bsort_buckets;
+
+/* Launch tuning; NULL or zero fields mean the library default. */
+typedef struct {
+    int32_t tile_keys;       /* words per odd-even transposition tile: a power of
+                                two in [128, 4096]; clamped per key width */
+    int32_t merge_threads;   /* threads per merge-split workgroup: 64..1024, multiple of 64 */
+    int32_t flags;           /* BSORT_FLAG_* */
+} bsort_tuning;
+
+/* The plain form: one kernel launch per (request, length) sub-array and per
+ * merge-split phase, with a host synchronisation to read the sub-array
+ * sizes.  Same result; for comparison with the batched form. */
+#define BSORT_FLAG_PER_BUCKET_LAUNCH 1
+/* Testing only: stop after the tile sorts (no merge-split); perm then holds
+ * each tile sorted on its own. */
+#define BSORT_FLAG_TILES_ONLY 2
+
+/* Plans only: a HIP event is recorded between stages inside the captured
+ * graph, so bsort_plan_stage_ms can report each stage's device time for the
+ * last execute.  Other entry points ignore this flag. */
+#define BSORT_FLAG_STAGE_EVENTS 4
+
+/* Workspace bytes for up to total_words words in up to n_requests lists with
+ * words of at most max_len bytes.  Returns 0 for invalid arguments. */
+size_t bsort_workspace_bytes(int64_t total_words, int32_t max_len, int32_t n_requests);
+
+/*
+ * Distribute words into sub-arrays by length (Section II phase 2; Section III
+ * approach two's count array): fills b->counts, b->starts and b->order.
+ * Stable: inside a length, order keeps input order.
+ */
+bsort_status bsort_bucketize(const bsort_words *w, const bsort_buckets *b,
+                             void *ws, size_t ws_bytes, bsort_stream_t stream);
+
+/*
+ * Sort each sub-array made by bsort_bucketize (same w and b) in byte order
+ * and write the final order to perm (device [n_words]): Section II phase 3
+ * with bubble sort run as odd-even transposition sort, plus block
+ * merge-split for sub-arrays longer than one tile.  b is read only.  Use the
+ * workspace the matching bsort_bucketize used: bsort_bucketize and
+ * bsort_sort_batch clear the device status word when they start, and this
+ * call adds its own faults to it.
+ */
+bsort_status bsort_sort_buckets(const bsort_words *w, const bsort_buckets *b,
+                                int32_t *perm, const bsort_tuning *t,
+                                void *ws, size_t ws_bytes, bsort_stream_t stream);
+
+/* R independent lists stored back to back. */
+typedef struct {
+    const uint8_t *bytes;        /* device [n_bytes] */
+    int64_t n_bytes;
+    const int64_t *offsets;      /* device [total_words+1], global byte offsets */
+    const int64_t *req_start;    /* device [n_requests+1]: list r holds global words
+                                    req_start[r] .. req_start[r+1]-1; req_start[0] = 0 */
+    const int64_t *h_req_start;  /* host copy of req_start (sizes the launch, no sync) */
+    int32_t n_requests;
+    int32_t max_len;
+} bsort_batch;
+
+/*
+ * Sort every list of a batch at once: all sub-arrays of all lists go through
+ * one sequence of launches.  perm (device [total_words]): for global position
+ * g in list r, perm[g] is the list-local index of the word at list-local
+ * sorted position g - req_start[r].
+ */
+bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_tuning *t,
+                              void *ws, size_t ws_bytes, bsort_stream_t stream);
+
+/*
+ * A captured batch: bsort_sort_batch's launches recorded once into a HIP
+ * graph for batches within the given capacity, then replayed by
+ * bsort_plan_execute with one graph launch (plus one small launch that
+ * passes the batch's pointers and sizes).  The plan owns a small device
+ * buffer and the graph; the workspace still comes from the caller and must
+ * hold bsort_plan_workspace_bytes(plan) bytes.
+ */
+typedef struct bsort_plan bsort_plan;
+bsort_status bsort_plan_create(bsort_plan **plan, int64_t cap_words, int32_t cap_requests,
+                               int64_t cap_request_words, int32_t max_len,
+                               const bsort_tuning *t, bsort_stream_t stream);
+size_t bsort_plan_workspace_bytes(const bsort_plan *plan);
+bsort_status bsort_plan_execute(bsort_plan *plan, const bsort_batch *b, int32_t *perm,
+                                void *ws, size_t ws_bytes, bsort_stream_t stream);
+void bsort_plan_destroy(bsort_plan *plan);
+
+/* Stage timing of a plan built with BSORT_FLAG_STAGE_EVENTS: the number of
+ * stages (0 without the flag), the name of stage i ("bucketize", "pack",
+ * "oets_d<D>" per record width D = ceil(L/4)+1, "merge_split"), and the
+ * device milliseconds of each stage in the plan's last execute, written to
+ * ms[0..n-1].  bsort_plan_stage_ms waits for that execute to finish. */
+int bsort_plan_stage_count(const bsort_plan *plan);
+const char *bsort_plan_stage_name(const bsort_plan *plan, int i);
+bsort_status bsort_plan_stage_ms(bsort_plan *plan, float *ms, int n);
+
+/* Synchronises the stream and returns the status word a previous call left
+ * in ws (BSORT_OK if none), then clears it. */
+bsort_status bsort_get_device_status(void *ws, bsort_stream_t stream);
+
+const char *bsort_status_string(bsort_status s);
+/* Detail of the last failure on this thread (e.g. the HIP error string). */
+const char *bsort_last_error(void);
+/* Library version, e.g. "bsort 0.1 gfx950". */
+const char *bsort_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSORT_H */

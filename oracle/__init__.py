@@ -12,8 +12,9 @@ Contents
   first.  Plain C (``bsort_oracle.c``), optionally one sub-array per OpenMP
   thread ("Bubble sort in OpenMP").
 * ``bubble_sort_batch`` -- the same over many independent word lists.
-* ``definition_sort`` -- the result's definition written out: the permutation
-  ordering words by (length, unsigned bytes, original index), via qsort.
+* ``definition_sort`` / ``definition_sort_batch`` -- the result's definition
+  written out: the permutation ordering words by (length, unsigned bytes,
+  original index), via qsort_r.
 * ``bucketize`` -- sub-array sizes, their exclusive scan, and the unsorted
   sub-array contents (the paper's count array and sub-array fill).
 * ``pack_keys`` -- fixed-width big-endian uint64 key lanes of equal-length
@@ -88,10 +89,12 @@ def _load(path: str):
     L.oracle_bubble_sort_batch.argtypes = [P, i64, P, P, i32, i32, ctypes.c_int,
                                            ctypes.c_int, P, P]
     L.oracle_definition_sort.argtypes = [P, i64, P, i32, P]
+    L.oracle_definition_sort_batch.argtypes = [P, i64, P, P, i32, ctypes.c_int, P]
     L.oracle_pack_keys.argtypes = [P, P, P, i32, i32, P]
     L.oracle_max_threads.argtypes = []
     for f in (L.oracle_bucketize, L.oracle_bubble_sort, L.oracle_bubble_sort_batch,
-              L.oracle_definition_sort, L.oracle_pack_keys, L.oracle_max_threads):
+              L.oracle_definition_sort, L.oracle_definition_sort_batch, L.oracle_pack_keys,
+              L.oracle_max_threads):
         f.restype = ctypes.c_int
     return L
 
@@ -181,6 +184,18 @@ def definition_sort(bytes_, offsets):
     _check(lib().oracle_definition_sort(_ptr(b), nb, _ptr(o), n, _ptr(perm)),
            "definition_sort")
     return perm[:n]
+
+
+def definition_sort_batch(bytes_, offsets, req_start, threads: int = 1):
+    """The definition per list over back-to-back lists; list-local perm."""
+    b, o, nb = _prep(bytes_, offsets)
+    rs = np.ascontiguousarray(req_start, dtype=np.int64)
+    R = len(rs) - 1
+    total = int(rs[-1]) if R >= 0 else 0
+    perm = np.zeros(max(total, 1), np.int32)
+    _check(lib().oracle_definition_sort_batch(_ptr(b), nb, _ptr(o), _ptr(rs), R, threads,
+                                              _ptr(perm)), "definition_sort_batch")
+    return perm[:total]
 
 
 def pack_keys(bytes_, offsets, idx, L: int) -> np.ndarray:

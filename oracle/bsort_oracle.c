@@ -28,6 +28,7 @@
  *   - a word's "number of characters" is its byte count;
  *   - a length-0 word is legal and forms sub-array 0.
  */
+#define _GNU_SOURCE
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -208,19 +209,22 @@ int oracle_bubble_sort_batch(const uint8_t *bytes, int64_t n_bytes, const int64_
 /*
  * Definition of the result, written out directly: the permutation that
  * orders words by (length, bytes as unsigned, original index).  A library
- * sort (qsort) does the ordering; the key is a total order, so the result is
- * unique and qsort's lack of stability does not matter.
+ * sort (qsort_r) does the ordering; the key is a total order, so the result
+ * is unique and qsort's lack of stability does not matter.
  */
-static const uint8_t *g_bytes;
-static const int64_t *g_offsets;
+typedef struct {
+    const uint8_t *bytes;
+    const int64_t *offsets;
+} def_ctx;
 
-static int cmp_definition(const void *pa, const void *pb)
+static int cmp_definition(const void *pa, const void *pb, void *arg)
 {
+    const def_ctx *c = (const def_ctx *)arg;
     int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
-    int64_t la = g_offsets[a + 1] - g_offsets[a], lb = g_offsets[b + 1] - g_offsets[b];
+    int64_t la = c->offsets[a + 1] - c->offsets[a], lb = c->offsets[b + 1] - c->offsets[b];
     if (la != lb) return la < lb ? -1 : 1;
-    int c = memcmp(g_bytes + g_offsets[a], g_bytes + g_offsets[b], (size_t)la);
-    if (c != 0) return c;
+    int r = memcmp(c->bytes + c->offsets[a], c->bytes + c->offsets[b], (size_t)la);
+    if (r != 0) return r;
     return a < b ? -1 : (a > b ? 1 : 0);
 }
 
@@ -232,10 +236,33 @@ int oracle_definition_sort(const uint8_t *bytes, int64_t n_bytes, const int64_t 
         if (offsets[i] < 0 || offsets[i + 1] < offsets[i] || offsets[i + 1] > n_bytes)
             return ORACLE_E_INVALID;
     for (int32_t i = 0; i < n; ++i) perm[i] = i;
-    g_bytes = bytes;
-    g_offsets = offsets;
-    qsort(perm, (size_t)n, sizeof(int32_t), cmp_definition);
+    def_ctx c = {bytes, offsets};
+    qsort_r(perm, (size_t)n, sizeof(int32_t), cmp_definition, &c);
     return ORACLE_OK;
+}
+
+/* The definition over back-to-back lists (see oracle_bubble_sort_batch);
+ * lists are spread over n_threads threads. */
+int oracle_definition_sort_batch(const uint8_t *bytes, int64_t n_bytes, const int64_t *offsets,
+                                 const int64_t *req_start, int32_t R, int n_threads,
+                                 int32_t *perm)
+{
+    int rc_all = ORACLE_OK;
+#ifdef _OPENMP
+    int nt = n_threads > 1 ? n_threads : 1;
+    #pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#endif
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t a = req_start[r], b = req_start[r + 1];
+        int rc = oracle_definition_sort(bytes, n_bytes, offsets + a, (int32_t)(b - a), perm + a);
+        if (rc != ORACLE_OK) {
+#ifdef _OPENMP
+            #pragma omp critical
+#endif
+            { if (rc_all == ORACLE_OK) rc_all = rc; }
+        }
+    }
+    return rc_all;
 }
 
 /*

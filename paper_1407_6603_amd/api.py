@@ -1,0 +1,228 @@
+"""Python entry points over the libbsort C ABI.
+
+Argument marshalling only: torch provides device memory and the current HIP
+stream; every step of the sort runs in libbsort's kernels.  All functions
+raise if the HIP library is missing or no GPU is visible.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+
+Tuning = _lib.Tuning
+BsortError = _lib.BsortError
+FLAG_PER_BUCKET_LAUNCH = _lib.FLAG_PER_BUCKET_LAUNCH
+FLAG_TILES_ONLY = _lib.FLAG_TILES_ONLY
+FLAG_STAGE_EVENTS = _lib.FLAG_STAGE_EVENTS
+MAX_LEN = _lib.BSORT_MAX_LEN
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("libbsort runs on a ROCm GPU (gfx950); none is visible")
+    _lib.load()
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None or t.numel() == 0:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_words(bytes_t: torch.Tensor, offsets_t: torch.Tensor):
+    if bytes_t.dtype != torch.uint8 or offsets_t.dtype != torch.int64:
+        raise TypeError("bytes must be uint8 and offsets int64")
+    if not (bytes_t.is_cuda and offsets_t.is_cuda):
+        raise ValueError("bytes and offsets must be device tensors")
+    if not (bytes_t.is_contiguous() and offsets_t.is_contiguous()):
+        raise ValueError("bytes and offsets must be contiguous")
+    if offsets_t.dim() != 1 or offsets_t.numel() < 1:
+        raise ValueError("offsets must be 1-D with n_words+1 entries")
+
+
+def tuning(tile_keys: int = 0, merge_threads: int = 0, flags: int = 0) -> Tuning:
+    return Tuning(tile_keys, merge_threads, flags)
+
+
+def workspace_bytes(total_words: int, max_len: int, n_requests: int = 1) -> int:
+    n = _lib.load().bsort_workspace_bytes(int(total_words), int(max_len), int(n_requests))
+    if n == 0:
+        raise ValueError("invalid workspace size arguments")
+    return int(n)
+
+
+class Workspace:
+    """Caller-owned device scratch (a uint8 tensor viewed at a 256-byte
+    aligned offset).  Reuse one per stream; it grows on demand."""
+
+    def __init__(self, nbytes: int = 0, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.tensor = None
+        self.nbytes = 0
+        if nbytes:
+            self.ensure(nbytes)
+
+    def ensure(self, nbytes: int):
+        if nbytes > self.nbytes:
+            self.tensor = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.nbytes = nbytes
+        return self
+
+    @property
+    def ptr(self) -> int:
+        p = self.tensor.data_ptr()
+        return (p + 255) & ~255
+
+
+def _ws_for(ws: Optional[Workspace], nbytes: int, device) -> Workspace:
+    if ws is None:
+        ws = Workspace(device=device)
+    return ws.ensure(nbytes)
+
+
+def bucketize(bytes_t: torch.Tensor, offsets_t: torch.Tensor, max_len: int,
+              ws: Optional[Workspace] = None, stream=None
+              ) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    """Sub-arrays by length: (counts[max_len+1], starts[max_len+2], order[n])."""
+    _require_gpu()
+    _check_words(bytes_t, offsets_t)
+    n = offsets_t.numel() - 1
+    dev = offsets_t.device
+    counts = torch.empty(max_len + 1, dtype=torch.int32, device=dev)
+    starts = torch.empty(max_len + 2, dtype=torch.int32, device=dev)
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = _ws_for(ws, workspace_bytes(n, max_len, 1), dev)
+    w = _lib.Words(_ptr(bytes_t), bytes_t.numel(), _ptr(offsets_t), n, max_len)
+    b = _lib.Buckets(_ptr(counts), _ptr(starts), _ptr(order))
+    _lib.check(_lib.load().bsort_bucketize(ctypes.byref(w), ctypes.byref(b), ws.ptr,
+                                           ws.nbytes, _stream(stream)))
+    return counts, starts, order
+
+
+def sort_buckets(bytes_t: torch.Tensor, offsets_t: torch.Tensor, counts: torch.Tensor,
+                 starts: torch.Tensor, order: torch.Tensor, max_len: int,
+                 tune: Optional[Tuning] = None, ws: Optional[Workspace] = None,
+                 stream=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Sort the sub-arrays made by bucketize; returns perm[n] (int32)."""
+    _require_gpu()
+    _check_words(bytes_t, offsets_t)
+    n = offsets_t.numel() - 1
+    dev = offsets_t.device
+    perm = out if out is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    ws = _ws_for(ws, workspace_bytes(n, max_len, 1), dev)
+    w = _lib.Words(_ptr(bytes_t), bytes_t.numel(), _ptr(offsets_t), n, max_len)
+    b = _lib.Buckets(_ptr(counts), _ptr(starts), _ptr(order))
+    _lib.check(_lib.load().bsort_sort_buckets(
+        ctypes.byref(w), ctypes.byref(b), _ptr(perm),
+        ctypes.byref(tune) if tune is not None else None, ws.ptr, ws.nbytes, _stream(stream)))
+    return perm
+
+
+def sort(bytes_t: torch.Tensor, offsets_t: torch.Tensor, max_len: int,
+         tune: Optional[Tuning] = None, ws: Optional[Workspace] = None,
+         stream=None) -> torch.Tensor:
+    """bucketize then sort_buckets: the final order of one word list."""
+    counts, starts, order = bucketize(bytes_t, offsets_t, max_len, ws, stream)
+    return sort_buckets(bytes_t, offsets_t, counts, starts, order, max_len, tune, ws, stream)
+
+
+def sort_batch(bytes_t: torch.Tensor, offsets_t: torch.Tensor, req_start_t: torch.Tensor,
+               h_req_start: np.ndarray, max_len: int, tune: Optional[Tuning] = None,
+               ws: Optional[Workspace] = None, stream=None,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Sort R lists stored back to back; perm holds list-local indices."""
+    _require_gpu()
+    _check_words(bytes_t, offsets_t)
+    h = np.ascontiguousarray(h_req_start, dtype=np.int64)
+    R = len(h) - 1
+    total = int(h[-1]) if R > 0 else 0
+    dev = offsets_t.device
+    perm = out if out is not None else torch.empty(total, dtype=torch.int32, device=dev)
+    ws = _ws_for(ws, workspace_bytes(total, max_len, max(R, 0)), dev)
+    b = _lib.Batch(_ptr(bytes_t), bytes_t.numel(), _ptr(offsets_t), _ptr(req_start_t),
+                   h.ctypes.data, R, max_len)
+    _lib.check(_lib.load().bsort_sort_batch(
+        ctypes.byref(b), _ptr(perm), ctypes.byref(tune) if tune is not None else None,
+        ws.ptr, ws.nbytes, _stream(stream)))
+    return perm
+
+
+def device_status(ws: Workspace, stream=None) -> int:
+    """Synchronise and return (then clear) the workspace status word."""
+    return int(_lib.load().bsort_get_device_status(ws.ptr, _stream(stream)))
+
+
+def check_device_status(ws: Workspace, stream=None):
+    _lib.check(device_status(ws, stream))
+
+
+class Plan:
+    """A batch sort captured into a HIP graph for batches up to a capacity."""
+
+    def __init__(self, cap_words: int, cap_requests: int, cap_request_words: int, max_len: int,
+                 tune: Optional[Tuning] = None, stream=None):
+        _require_gpu()
+        self._lib = _lib.load()
+        self._p = ctypes.c_void_p()
+        _lib.check(self._lib.bsort_plan_create(
+            ctypes.byref(self._p), int(cap_words), int(cap_requests), int(cap_request_words),
+            int(max_len), ctypes.byref(tune) if tune is not None else None, _stream(stream)))
+        self.max_len = max_len
+        self.workspace_bytes = int(self._lib.bsort_plan_workspace_bytes(self._p))
+
+    def execute(self, bytes_t, offsets_t, req_start_t, h_req_start, ws: Workspace,
+                stream=None, out: Optional[torch.Tensor] = None, max_len: Optional[int] = None):
+        _check_words(bytes_t, offsets_t)
+        h = np.ascontiguousarray(h_req_start, dtype=np.int64)
+        R = len(h) - 1
+        total = int(h[-1]) if R > 0 else 0
+        perm = out if out is not None else torch.empty(total, dtype=torch.int32,
+                                                       device=offsets_t.device)
+        ws.ensure(self.workspace_bytes)
+        ml = self.max_len if max_len is None else max_len
+        b = _lib.Batch(_ptr(bytes_t), bytes_t.numel(), _ptr(offsets_t), _ptr(req_start_t),
+                       h.ctypes.data, R, ml)
+        _lib.check(self._lib.bsort_plan_execute(self._p, ctypes.byref(b), _ptr(perm), ws.ptr,
+                                                ws.nbytes, _stream(stream)))
+        return perm
+
+    def stage_names(self):
+        n = self._lib.bsort_plan_stage_count(self._p)
+        return [self._lib.bsort_plan_stage_name(self._p, i).decode() for i in range(n)]
+
+    def stage_ms(self):
+        """Per-stage device milliseconds of the last execute (waits for it)."""
+        n = self._lib.bsort_plan_stage_count(self._p)
+        arr = (ctypes.c_float * max(n, 1))()
+        _lib.check(self._lib.bsort_plan_stage_ms(self._p, arr, n))
+        return dict(zip(self.stage_names(), [float(x) for x in arr[:n]]))
+
+    def close(self):
+        if self._p:
+            self._lib.bsort_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_device(bytes_np: np.ndarray, offsets_np: np.ndarray, device="cuda"):
+    """Host word arrays -> device tensors (uint8 bytes, int64 offsets)."""
+    b = torch.from_numpy(np.ascontiguousarray(bytes_np, dtype=np.uint8))
+    if b.numel() == 0:
+        b = torch.zeros(1, dtype=torch.uint8)
+    o = torch.from_numpy(np.ascontiguousarray(offsets_np, dtype=np.int64))
+    return b.to(device), o.to(device)

@@ -1,0 +1,596 @@
+// C ABI of libbsort: argument checks, workspace layout, launch sequences,
+// the plain per-bucket form and captured plans.  See include/bsort.h.
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/bsort.h"
+#include "bsort_internal.h"
+
+using namespace bsort;
+
+namespace {
+
+thread_local std::string g_err;
+
+bsort_status fail(bsort_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(BSORT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kDefaultTile = 1024;
+constexpr int kDefaultMergeThreads = 256;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout: a pure function of (total words, lists, max_len), so the
+// size a caller asks for and the layout a call uses always agree.
+struct Layout {
+    size_t status, job, chunk_begin, chunk_hist, key_off, keys, tiles[kNumD], tile_count,
+        mlist[2], mcount, counts, starts, order, jobs;
+    int64_t chunk_cap, tile_cap, merge_cap;
+    int32_t phase_cap, ml1, dmax, wmax;
+    size_t bytes;
+};
+
+bool make_layout(int64_t total, int32_t R, int32_t max_len, Layout& L) {
+    if (total < 0 || R < 0 || max_len < 0 || max_len > BSORT_MAX_LEN) return false;
+    memset(&L, 0, sizeof(L));
+    L.ml1 = max_len + 1;
+    L.dmax = max_len >= 1 ? dwords_for_len(max_len) : 1;
+    L.wmax = lanes_for_len(max_len);
+    const int64_t tiles_total = (total + kMinTile - 1) / kMinTile;
+    L.chunk_cap = (total + kChunk - 1) / kChunk + R;
+    L.tile_cap = tiles_total + 4 * (int64_t)R;
+    L.merge_cap = (tiles_total + (int64_t)R * L.ml1) / 2 + 1;
+    L.phase_cap = (int32_t)std::min<int64_t>(tiles_total + 2, kMaxPhaseCap);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    L.status = take(256);
+    L.job = take(sizeof(Job));
+    L.chunk_begin = take(sizeof(int64_t) * ((size_t)R + 1));
+    L.chunk_hist = take(sizeof(int32_t) * (size_t)L.chunk_cap * L.ml1);
+    L.key_off = take(sizeof(int64_t) * (size_t)R * L.ml1);
+    L.keys = take(sizeof(uint64_t) * (size_t)L.wmax * (size_t)total);
+    for (int D = 2; D <= L.dmax && D <= kMaxD; ++D)
+        L.tiles[D] = take(sizeof(TileDesc) * (size_t)L.tile_cap);
+    L.tile_count = take(sizeof(int32_t) * kNumD);
+    L.mlist[0] = take(sizeof(MergeItem) * (size_t)L.merge_cap);
+    L.mlist[1] = take(sizeof(MergeItem) * (size_t)L.merge_cap);
+    L.mcount = take(sizeof(int32_t) * ((size_t)L.phase_cap + 1));
+    L.counts = take(sizeof(int32_t) * (size_t)R * L.ml1);
+    L.starts = take(sizeof(int32_t) * (size_t)R * (L.ml1 + 1));
+    L.order = take(sizeof(int32_t) * (size_t)total);
+    L.jobs = take(sizeof(Job) * (size_t)R);
+    L.bytes = off;
+    return true;
+}
+
+bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+bsort_status check_tuning(const bsort_tuning* t) {
+    if (!t) return BSORT_OK;
+    if (t->tile_keys != 0 && (!pow2(t->tile_keys) || t->tile_keys < kMinTile || t->tile_keys > 4096))
+        return fail(BSORT_E_INVALID, "tile_keys must be 0 or a power of two in [128, 4096]");
+    if (t->merge_threads != 0 &&
+        (t->merge_threads < 64 || t->merge_threads > 1024 || t->merge_threads % 64))
+        return fail(BSORT_E_INVALID, "merge_threads must be 0 or a multiple of 64 in [64, 1024]");
+    if (t->flags & ~(BSORT_FLAG_PER_BUCKET_LAUNCH | BSORT_FLAG_TILES_ONLY |
+                     BSORT_FLAG_STAGE_EVENTS))
+        return fail(BSORT_E_INVALID, "unknown flag");
+    return BSORT_OK;
+}
+
+Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
+                   const bsort_tuning* t) {
+    Bounds b;
+    memset(&b, 0, sizeof(b));
+    b.total = total;
+    b.R = R;
+    b.ml1 = L.ml1;
+    b.chunk_cap = L.chunk_cap;
+    b.tile_cap = L.tile_cap;
+    b.dmax = L.dmax;
+    b.flags = t ? t->flags : 0;
+    const int want = (t && t->tile_keys) ? t->tile_keys : kDefaultTile;
+    int tmin = 1 << 30, lds = 0;
+    for (int D = 2; D <= kMaxD; ++D) {
+        int T = std::min(want, kWave * kmax_for(D));
+        b.tile_keys[D] = T;
+        if (D <= L.dmax) {
+            tmin = std::min(tmin, T);
+            lds = std::max(lds, D * 2 * T * 4);
+        }
+    }
+    b.merge_threads = (t && t->merge_threads) ? t->merge_threads : kDefaultMergeThreads;
+    b.merge_lds = lds;
+    int64_t pb = 0;
+    if (L.dmax >= 2 && n_max >= 2) pb = (n_max + tmin - 1) / tmin;
+    b.phase_bound = (int32_t)std::min<int64_t>(pb, L.phase_cap);
+    return b;
+}
+
+// Job for the call, pointers into the workspace per the layout.
+Job base_job(const Layout& L, char* ws, const Bounds& b) {
+    Job j;
+    memset(&j, 0, sizeof(j));
+    j.ml1 = L.ml1;
+    j.max_len = L.ml1 - 1;
+    j.flags = b.flags;
+    j.status = (uint32_t*)(ws + L.status);
+    j.chunk_begin = (int64_t*)(ws + L.chunk_begin);
+    j.chunk_hist = (int32_t*)(ws + L.chunk_hist);
+    j.chunk_cap = L.chunk_cap;
+    j.key_off = (int64_t*)(ws + L.key_off);
+    j.keys = (uint64_t*)(ws + L.keys);
+    for (int D = 2; D <= kMaxD; ++D) {
+        if (D <= L.dmax) {
+            j.tiles[D] = (TileDesc*)(ws + L.tiles[D]);
+            j.tile_cap[D] = L.tile_cap;
+        }
+        j.tile_keys[D] = b.tile_keys[D];
+    }
+    j.tile_count = (int32_t*)(ws + L.tile_count);
+    j.mlist[0] = (MergeItem*)(ws + L.mlist[0]);
+    j.mlist[1] = (MergeItem*)(ws + L.mlist[1]);
+    j.merge_cap = L.merge_cap;
+    j.mcount = (int32_t*)(ws + L.mcount);
+    j.phase_cap = L.phase_cap;
+    return j;
+}
+
+bsort_status check_ws(const Layout& L, void* ws, size_t ws_bytes) {
+    if (!ws) return fail(BSORT_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(BSORT_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < L.bytes)
+        return fail(BSORT_E_WORKSPACE, "workspace has " + std::to_string(ws_bytes) +
+                                           " bytes, needs " + std::to_string(L.bytes));
+    return BSORT_OK;
+}
+
+bsort_status check_words(const bsort_words* w) {
+    if (!w) return fail(BSORT_E_INVALID, "words is NULL");
+    if (w->max_len < 0) return fail(BSORT_E_INVALID, "max_len < 0");
+    if (w->max_len > BSORT_MAX_LEN) return fail(BSORT_E_TOO_LONG, "max_len > BSORT_MAX_LEN");
+    if (w->n_words < 0 || w->n_bytes < 0) return fail(BSORT_E_INVALID, "negative size");
+    if (w->n_words > 0 && !w->offsets) return fail(BSORT_E_INVALID, "offsets is NULL");
+    if (w->n_bytes > 0 && !w->bytes) return fail(BSORT_E_INVALID, "bytes is NULL");
+    return BSORT_OK;
+}
+
+bsort_status check_buckets(const bsort_buckets* b, int32_t n) {
+    if (!b || !b->counts || !b->starts) return fail(BSORT_E_INVALID, "buckets arrays are NULL");
+    if (n > 0 && !b->order) return fail(BSORT_E_INVALID, "order is NULL");
+    return BSORT_OK;
+}
+
+// job of a single list (words w) with req_start held inside the device job
+Job single_job(const Layout& L, char* ws, Job* jdst, const Bounds& bd, const bsort_words* w) {
+    Job j = base_job(L, ws, bd);
+    j.bytes = w->bytes;
+    j.n_bytes = w->n_bytes;
+    j.offsets = w->offsets;
+    j.total = w->n_words;
+    j.R = 1;
+    j.max_len = w->max_len;
+    j.rs_inline[0] = 0;
+    j.rs_inline[1] = w->n_words;
+    j.req_start = (const int64_t*)((char*)jdst + offsetof(Job, rs_inline));
+    return j;
+}
+
+bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
+                        const Layout& L, char* ws, hipStream_t s);
+
+}  // namespace
+
+struct bsort_plan {
+    int64_t cap_words;
+    int64_t cap_req;
+    int32_t cap_R;
+    int32_t max_len;
+    bsort_tuning tun;
+    Layout lay;
+    Bounds bd;
+    Job* job_dev;
+    hipGraphExec_t exec;
+    std::vector<hipEvent_t> ev;          // stage boundaries (BSORT_FLAG_STAGE_EVENTS)
+    std::vector<std::string> stage_names;
+};
+
+extern "C" {
+
+size_t bsort_workspace_bytes(int64_t total_words, int32_t max_len, int32_t n_requests) {
+    Layout L;
+    if (!make_layout(total_words, n_requests, max_len, L)) return 0;
+    return L.bytes;
+}
+
+bsort_status bsort_bucketize(const bsort_words* w, const bsort_buckets* b, void* ws,
+                             size_t ws_bytes, bsort_stream_t stream) {
+    bsort_status st = check_words(w);
+    if (st != BSORT_OK) return st;
+    if ((st = check_buckets(b, w->n_words)) != BSORT_OK) return st;
+    Layout L;
+    make_layout(w->n_words, 1, w->max_len, L);
+    if ((st = check_ws(L, ws, ws_bytes)) != BSORT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Bounds bd = make_bounds(L, w->n_words, 1, w->n_words, nullptr);
+    Job* jd = (Job*)((char*)ws + L.job);
+    Job j = single_job(L, (char*)ws, jd, bd, w);
+    j.counts = b->counts;
+    j.starts = b->starts;
+    j.order = b->order;
+    HIP_TRY(launch_set_job(j, jd, s));
+    HIP_TRY(launch_bucketize(jd, bd, s));
+    return BSORT_OK;
+}
+
+bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, int32_t* perm,
+                                const bsort_tuning* t, void* ws, size_t ws_bytes,
+                                bsort_stream_t stream) {
+    bsort_status st = check_words(w);
+    if (st != BSORT_OK) return st;
+    if ((st = check_buckets(b, w->n_words)) != BSORT_OK) return st;
+    if ((st = check_tuning(t)) != BSORT_OK) return st;
+    if (w->n_words > 0 && !perm) return fail(BSORT_E_INVALID, "perm is NULL");
+    if (t && (t->flags & BSORT_FLAG_PER_BUCKET_LAUNCH))
+        return fail(BSORT_E_INVALID, "the per-bucket form is a bsort_sort_batch flag");
+    Layout L;
+    make_layout(w->n_words, 1, w->max_len, L);
+    if ((st = check_ws(L, ws, ws_bytes)) != BSORT_OK) return st;
+    if (w->n_words == 0) return BSORT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Bounds bd = make_bounds(L, w->n_words, 1, w->n_words, t);
+    Job* jd = (Job*)((char*)ws + L.job);
+    Job j = single_job(L, (char*)ws, jd, bd, w);
+    j.counts = b->counts;
+    j.starts = b->starts;
+    j.order = b->order;
+    j.perm = perm;
+    HIP_TRY(launch_set_job(j, jd, s));
+    HIP_TRY(launch_sort(jd, bd, s));
+    return BSORT_OK;
+}
+
+static bsort_status check_batch(const bsort_batch* b, int32_t* perm, int64_t& total,
+                                int64_t& n_max) {
+    if (!b) return fail(BSORT_E_INVALID, "batch is NULL");
+    if (b->n_requests < 0) return fail(BSORT_E_INVALID, "n_requests < 0");
+    if (b->max_len < 0) return fail(BSORT_E_INVALID, "max_len < 0");
+    if (b->max_len > BSORT_MAX_LEN) return fail(BSORT_E_TOO_LONG, "max_len > BSORT_MAX_LEN");
+    if (b->n_bytes < 0) return fail(BSORT_E_INVALID, "n_bytes < 0");
+    total = 0;
+    n_max = 0;
+    if (b->n_requests == 0) return BSORT_OK;
+    if (!b->h_req_start || !b->req_start) return fail(BSORT_E_INVALID, "req_start is NULL");
+    if (b->h_req_start[0] != 0) return fail(BSORT_E_INVALID, "req_start[0] != 0");
+    for (int32_t r = 0; r < b->n_requests; ++r) {
+        const int64_t n = b->h_req_start[r + 1] - b->h_req_start[r];
+        if (n < 0) return fail(BSORT_E_INVALID, "req_start decreases");
+        if (n > INT32_MAX) return fail(BSORT_E_INVALID, "a list has 2^31 words or more");
+        n_max = std::max(n_max, n);
+    }
+    total = b->h_req_start[b->n_requests];
+    if (total > 0 && (!b->offsets || !perm)) return fail(BSORT_E_INVALID, "offsets or perm NULL");
+    if (b->n_bytes > 0 && !b->bytes) return fail(BSORT_E_INVALID, "bytes is NULL");
+    return BSORT_OK;
+}
+
+static Job batch_job(const Layout& L, char* ws, const Bounds& bd, const bsort_batch* b,
+                     int64_t total, int32_t* perm) {
+    Job j = base_job(L, ws, bd);
+    j.bytes = b->bytes;
+    j.n_bytes = b->n_bytes;
+    j.offsets = b->offsets;
+    j.req_start = b->req_start;
+    j.total = total;
+    j.R = b->n_requests;
+    j.max_len = b->max_len;
+    j.counts = (int32_t*)(ws + L.counts);
+    j.starts = (int32_t*)(ws + L.starts);
+    j.order = (int32_t*)(ws + L.order);
+    j.perm = perm;
+    return j;
+}
+
+bsort_status bsort_sort_batch(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
+                              void* ws, size_t ws_bytes, bsort_stream_t stream) {
+    int64_t total, n_max;
+    bsort_status st = check_batch(b, perm, total, n_max);
+    if (st != BSORT_OK) return st;
+    if ((st = check_tuning(t)) != BSORT_OK) return st;
+    Layout L;
+    make_layout(total, b->n_requests, b->max_len, L);
+    if ((st = check_ws(L, ws, ws_bytes)) != BSORT_OK) return st;
+    if (b->n_requests == 0) return BSORT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (t && (t->flags & BSORT_FLAG_PER_BUCKET_LAUNCH))
+        return plain_form(b, perm, t, L, (char*)ws, s);
+    Bounds bd = make_bounds(L, total, b->n_requests, n_max, t);
+    Job* jd = (Job*)((char*)ws + L.job);
+    Job j = batch_job(L, (char*)ws, bd, b, total, perm);
+    HIP_TRY(launch_set_job(j, jd, s));
+    HIP_TRY(launch_bucketize(jd, bd, s));
+    HIP_TRY(launch_sort(jd, bd, s));
+    return BSORT_OK;
+}
+
+bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap_requests,
+                               int64_t cap_request_words, int32_t max_len,
+                               const bsort_tuning* t, bsort_stream_t stream) {
+    (void)stream;
+    if (!plan) return fail(BSORT_E_INVALID, "plan is NULL");
+    *plan = nullptr;
+    if (cap_words < 0 || cap_requests < 1 || cap_request_words < 0 || max_len < 0)
+        return fail(BSORT_E_INVALID, "bad capacity");
+    if (max_len > BSORT_MAX_LEN) return fail(BSORT_E_TOO_LONG, "max_len > BSORT_MAX_LEN");
+    bsort_status st = check_tuning(t);
+    if (st != BSORT_OK) return st;
+    if (t && (t->flags & BSORT_FLAG_PER_BUCKET_LAUNCH))
+        return fail(BSORT_E_INVALID, "a plan cannot use the per-bucket form");
+    bsort_plan* p = new (std::nothrow) bsort_plan();
+    if (!p) return fail(BSORT_E_NO_MEMORY, "plan allocation");
+    p->cap_words = cap_words;
+    p->cap_req = std::min<int64_t>(cap_request_words, cap_words);
+    p->cap_R = cap_requests;
+    p->max_len = max_len;
+    memset(&p->tun, 0, sizeof(p->tun));
+    if (t) p->tun = *t;
+    make_layout(cap_words, cap_requests, max_len, p->lay);
+    p->bd = make_bounds(p->lay, cap_words, cap_requests, p->cap_req, t);
+    p->job_dev = nullptr;
+    p->exec = nullptr;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipMalloc((void**)&p->job_dev, sizeof(Job));
+    if (e != hipSuccess) {
+        delete p;
+        return fail(BSORT_E_NO_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    e = hipSuccess;
+    const bool stage_events = t && (t->flags & BSORT_FLAG_STAGE_EVENTS);
+    if (stage_events) {
+        p->stage_names.push_back("bucketize");
+        p->stage_names.push_back("pack");
+        for (int D = 2; D <= p->bd.dmax && D <= kMaxD; ++D)
+            p->stage_names.push_back("oets_d" + std::to_string(D));
+        p->stage_names.push_back("merge_split");
+        p->ev.assign(p->stage_names.size() + 1, nullptr);
+        for (auto& ev : p->ev)
+            if (e == hipSuccess) e = hipEventCreate(&ev);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int k = 0;
+        auto mark = [&]() -> hipError_t {
+            return stage_events ? hipEventRecord(p->ev[k++], cs) : hipSuccess;
+        };
+        hipError_t e1 = mark();
+        if (e1 == hipSuccess) e1 = launch_bucketize(p->job_dev, p->bd, cs);
+        if (e1 == hipSuccess) e1 = mark();
+        if (e1 == hipSuccess) e1 = launch_sort_prep(p->job_dev, p->bd, cs);
+        for (int D = 2; D <= p->bd.dmax && D <= kMaxD && e1 == hipSuccess; ++D) {
+            e1 = mark();
+            if (e1 == hipSuccess) e1 = launch_oets_tiles_one(p->job_dev, p->bd, D, cs);
+        }
+        if (e1 == hipSuccess) e1 = mark();
+        if (e1 == hipSuccess) e1 = launch_merges(p->job_dev, p->bd, cs);
+        if (e1 == hipSuccess) e1 = mark();
+        e = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (cs) hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        for (auto ev : p->ev)
+            if (ev) hipEventDestroy(ev);
+        hipFree(p->job_dev);
+        delete p;
+        return fail(BSORT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *plan = p;
+    return BSORT_OK;
+}
+
+size_t bsort_plan_workspace_bytes(const bsort_plan* plan) { return plan ? plan->lay.bytes : 0; }
+
+bsort_status bsort_plan_execute(bsort_plan* p, const bsort_batch* b, int32_t* perm, void* ws,
+                                size_t ws_bytes, bsort_stream_t stream) {
+    if (!p) return fail(BSORT_E_INVALID, "plan is NULL");
+    int64_t total, n_max;
+    bsort_status st = check_batch(b, perm, total, n_max);
+    if (st != BSORT_OK) return st;
+    if (b->n_requests > p->cap_R || total > p->cap_words || n_max > p->cap_req ||
+        b->max_len > p->max_len)
+        return fail(BSORT_E_CAPACITY, "batch exceeds the plan's capacity");
+    if ((st = check_ws(p->lay, ws, ws_bytes)) != BSORT_OK) return st;
+    if (b->n_requests == 0) return BSORT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Job j = batch_job(p->lay, (char*)ws, p->bd, b, total, perm);
+    HIP_TRY(launch_set_job(j, p->job_dev, s));
+    HIP_TRY(hipGraphLaunch(p->exec, s));
+    return BSORT_OK;
+}
+
+int bsort_plan_stage_count(const bsort_plan* p) {
+    return p ? (int)p->stage_names.size() : 0;
+}
+
+const char* bsort_plan_stage_name(const bsort_plan* p, int i) {
+    if (!p || i < 0 || i >= (int)p->stage_names.size()) return nullptr;
+    return p->stage_names[i].c_str();
+}
+
+bsort_status bsort_plan_stage_ms(bsort_plan* p, float* ms, int n) {
+    if (!p || !ms) return fail(BSORT_E_INVALID, "plan or ms is NULL");
+    if (p->stage_names.empty()) return fail(BSORT_E_INVALID, "plan built without stage events");
+    if (n < (int)p->stage_names.size()) return fail(BSORT_E_INVALID, "ms too short");
+    HIP_TRY(hipEventSynchronize(p->ev.back()));
+    for (size_t i = 0; i < p->stage_names.size(); ++i)
+        HIP_TRY(hipEventElapsedTime(&ms[i], p->ev[i], p->ev[i + 1]));
+    return BSORT_OK;
+}
+
+void bsort_plan_destroy(bsort_plan* p) {
+    if (!p) return;
+    for (auto ev : p->ev)
+        if (ev) hipEventDestroy(ev);
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->job_dev) hipFree(p->job_dev);
+    delete p;
+}
+
+bsort_status bsort_get_device_status(void* ws, bsort_stream_t stream) {
+    if (!ws) return fail(BSORT_E_WORKSPACE, "workspace is NULL");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    uint32_t v = 0;
+    HIP_TRY(hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost));
+    if (v == 0) return BSORT_OK;
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpy(ws, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    std::string what;
+    if (v & ST_TOO_LONG) what += " word longer than max_len;";
+    if (v & ST_BAD_OFFSETS) what += " offsets decrease or pass n_bytes;";
+    if (v & ST_BAD_REQ) what += " request bounds inconsistent;";
+    if (v & ST_OVERFLOW) what += " internal list overflow;";
+    g_err = "device status:" + what;
+    if (v & ST_TOO_LONG) return BSORT_E_TOO_LONG;
+    return BSORT_E_INVALID;
+}
+
+const char* bsort_status_string(bsort_status s) {
+    switch (s) {
+        case BSORT_OK: return "ok";
+        case BSORT_E_INVALID: return "invalid argument";
+        case BSORT_E_TOO_LONG: return "word too long";
+        case BSORT_E_NO_MEMORY: return "out of memory";
+        case BSORT_E_WORKSPACE: return "workspace too small or misaligned";
+        case BSORT_E_HIP: return "HIP runtime error";
+        case BSORT_E_CAPACITY: return "batch exceeds plan capacity";
+    }
+    return "unknown status";
+}
+
+const char* bsort_last_error(void) { return g_err.c_str(); }
+
+const char* bsort_version(void) { return "bsort 0.1 gfx950"; }
+
+}  // extern "C"
+
+namespace {
+
+// The plain form: per list, the bucketize launches; one host
+// synchronisation to read every sub-array size; then per list one pack
+// launch and, per sub-array, one tile launch and one launch per merge-split
+// phase.
+bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
+                        const Layout& L, char* ws, hipStream_t s) {
+    const int32_t R = b->n_requests;
+    const int ml1 = L.ml1;
+    const int wmax = L.wmax;
+    const int64_t* h = b->h_req_start;
+    Job* jobs = (Job*)(ws + L.jobs);
+    Bounds bd0 = make_bounds(L, h[R], R, 0, t);
+    for (int32_t r = 0; r < R; ++r) {
+        const int64_t n = h[r + 1] - h[r];
+        Layout Lr;
+        make_layout(n, 1, L.ml1 - 1, Lr);
+        Bounds br = make_bounds(Lr, n, 1, n, t);
+        Job j = base_job(L, ws, bd0);
+        j.bytes = b->bytes;
+        j.n_bytes = b->n_bytes;
+        j.offsets = b->offsets + h[r];
+        j.total = n;
+        j.R = 1;
+        j.max_len = b->max_len;
+        j.rs_inline[0] = 0;
+        j.rs_inline[1] = n;
+        j.req_start = (const int64_t*)((char*)&jobs[r] + offsetof(Job, rs_inline));
+        j.counts = (int32_t*)(ws + L.counts) + (int64_t)r * ml1;
+        j.starts = (int32_t*)(ws + L.starts) + (int64_t)r * (ml1 + 1);
+        j.order = (int32_t*)(ws + L.order) + h[r];
+        j.perm = perm + h[r];
+        j.keys = (uint64_t*)(ws + L.keys) + (int64_t)wmax * h[r];
+        j.key_off = (int64_t*)(ws + L.key_off) + (int64_t)r * ml1;
+        j.chunk_cap = Lr.chunk_cap;
+        if (r > 0) j.flags |= kJobKeepStatus;
+        HIP_TRY(launch_set_job(j, &jobs[r], s));
+        br.chunk_cap = Lr.chunk_cap;
+        HIP_TRY(launch_bucketize(&jobs[r], br, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> cnt((size_t)R * ml1);
+    HIP_TRY(hipMemcpy(cnt.data(), ws + L.counts, sizeof(int32_t) * cnt.size(),
+                      hipMemcpyDeviceToHost));
+    std::vector<int64_t> ko((size_t)R * ml1);
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t run = 0;
+        for (int l = 0; l < ml1; ++l) {
+            ko[(size_t)r * ml1 + l] = run;
+            run += (int64_t)lanes_for_len(l) * cnt[(size_t)r * ml1 + l];
+        }
+    }
+    HIP_TRY(hipMemcpy(ws + L.key_off, ko.data(), sizeof(int64_t) * ko.size(),
+                      hipMemcpyHostToDevice));
+    const bool tiles_only = t && (t->flags & BSORT_FLAG_TILES_ONLY);
+    for (int32_t r = 0; r < R; ++r) {
+        const int64_t n = h[r + 1] - h[r];
+        if (n == 0) continue;
+        Layout Lr;
+        make_layout(n, 1, L.ml1 - 1, Lr);
+        Bounds br = make_bounds(Lr, n, 1, n, t);
+        HIP_TRY(launch_pack(&jobs[r], br, s));
+        int64_t start = 0;
+        for (int l = 0; l < ml1; ++l) {
+            const int nb = cnt[(size_t)r * ml1 + l];
+            const int64_t pos0 = start;
+            start += nb;
+            if (l == 0 || nb < 2) continue;
+            const int D = dwords_for_len(l);
+            const int T = bd0.tile_keys[D];
+            const int nt = (nb + T - 1) / T;
+            TileDesc td;
+            td.pos0 = pos0;
+            td.key_off = ko[(size_t)r * ml1 + l];
+            td.n_b = nb;
+            td.t0 = 0;
+            td.n = 0;
+            td.L = l;
+            HIP_TRY(launch_tile_one_bucket(&jobs[r], D, td, nt, T, nt > 1 && !tiles_only, s));
+            if (nt < 2 || tiles_only) continue;
+            MergeItem m;
+            m.pos0 = pos0;
+            m.key_off = td.key_off;
+            m.n_b = nb;
+            m.L = l;
+            m.T = T;
+            m.a = 0;
+            m.p = nt;
+            m.pad = 0;
+            const int lds = D * 2 * T * 4;
+            for (int ph = 0; ph < nt; ++ph) {
+                const int npairs = (nt - (ph & 1)) / 2;
+                HIP_TRY(launch_merge_one_bucket(&jobs[r], m, npairs, ph, bd0.merge_threads, lds, s));
+            }
+        }
+    }
+    return BSORT_OK;
+}
+
+}  // namespace

@@ -149,6 +149,8 @@ def pin_batch_matches_single(oracle):
             return f"batch list {r} differs"
     if cmp != total_cmp:
         return "batch comparison total"
+    if not np.array_equal(oracle.definition_sort_batch(b.bytes, b.offsets, b.req_start, 4), perm):
+        return "definition batch differs from bubble batch"
     return None
 
 

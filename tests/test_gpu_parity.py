@@ -1,0 +1,306 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Integer work: every comparison is bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import wordgen
+from tests.conftest import load_golden
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1407_6603_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ws(bs):
+    return bs.Workspace(device="cuda")
+
+
+def gpu_sort(bs, ws, w, max_len, tune=None):
+    b, o = bs.to_device(w.bytes, w.offsets)
+    perm = bs.sort(b, o, max_len, tune=tune, ws=ws)
+    bs.check_device_status(ws)
+    return perm.cpu().numpy()
+
+
+def gpu_batch(bs, ws, batch, max_len, tune=None):
+    b, o = bs.to_device(batch.bytes, batch.offsets)
+    rs = torch.from_numpy(batch.req_start).cuda()
+    perm = bs.sort_batch(b, o, rs, batch.req_start, max_len, tune=tune, ws=ws)
+    bs.check_device_status(ws)
+    return perm.cpu().numpy()
+
+
+def maxlen(w):
+    return int(np.diff(w.offsets).max()) if w.n else 0
+
+
+# ------------------------------------------------------------- single lists
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_bucketize_matches_oracle(bs, ws, k):
+    w = wordgen.single(k)
+    ml = wordgen.SINGLE[k].lmax
+    b, o = bs.to_device(w.bytes, w.offsets)
+    counts, starts, order = bs.bucketize(b, o, ml, ws=ws)
+    bs.check_device_status(ws)
+    c, s, od = oracle.bucketize(w.bytes, w.offsets, ml)
+    assert np.array_equal(counts.cpu().numpy(), c)
+    assert np.array_equal(starts.cpu().numpy(), s)
+    assert np.array_equal(order.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_sort_matches_bubble_oracle(bs, ws, k):
+    w = wordgen.single(k)
+    ml = wordgen.SINGLE[k].lmax
+    expect = oracle.bubble_sort(w.bytes, w.offsets, max_len=ml, threads=8)
+    assert np.array_equal(gpu_sort(bs, ws, w, ml), expect)
+
+
+def test_sort_workload3_full(bs, ws):
+    """250,000 words; buckets far beyond one tile (merge-split path)."""
+    w = wordgen.single(3)
+    expect = oracle.bubble_sort(w.bytes, w.offsets, max_len=24, threads=16)
+    assert np.array_equal(gpu_sort(bs, ws, w, 24), expect)
+
+
+@pytest.mark.parametrize("tile,mt", [(128, 256), (256, 64), (512, 256), (1024, 1024),
+                                     (2048, 128), (4096, 256), (0, 0)])
+def test_tuning_does_not_change_bits(bs, ws, tile, mt):
+    w = wordgen.single(2)
+    expect = oracle.definition_sort(w.bytes, w.offsets)
+    got = gpu_sort(bs, ws, w, 20, tune=bs.tuning(tile, mt))
+    assert np.array_equal(got, expect)
+
+
+def test_tiles_only_sorts_each_tile(bs, ws):
+    """With the merge-split switched off every tile is sorted on its own:
+    tile t of a sub-array is the sorted form of its slice of the stable
+    sub-array order (seams between tiles are not merged)."""
+    w = wordgen.single(2)
+    T = 128
+    got = gpu_sort(bs, ws, w, 20, tune=bs.tuning(T, 0, bs.FLAG_TILES_ONLY))
+    counts, starts, order = oracle.bucketize(w.bytes, w.offsets, 20)
+    wl = w.as_list()
+    for L in range(1, 21):
+        a, n = int(starts[L]), int(counts[L])
+        if n < 2:
+            continue
+        for t0 in range(0, n, T):
+            idx = order[a + t0:a + min(n, t0 + T)]
+            exp = sorted(idx.tolist(), key=lambda i: (wl[i], i))
+            assert got[a + t0:a + t0 + len(idx)].tolist() == exp
+
+
+@pytest.mark.parametrize("name", ["hand_sentence.txt", "hand_bytes.txt"])
+def test_golden_fixtures(bs, ws, name):
+    wl, perm, counts = load_golden(name)
+    w = wordgen.Words.from_list(wl)
+    assert gpu_sort(bs, ws, w, maxlen(w)).tolist() == perm
+
+
+def edge_cases():
+    rng = np.random.default_rng(2024)
+    cases = {
+        "one_word": wordgen.Words.from_list([b"x"]),
+        "two_equal": wordgen.Words.from_list([b"ab", b"ab"]),
+        "all_equal_5000": wordgen.Words.from_list([b"same"] * 5000),
+        "empty_words_only": wordgen.Words.from_list([b""] * 100),
+        "empty_and_short": wordgen.Words.from_list([b"", b"b", b"", b"a", b"", b"ab", b"A"]),
+        "high_bytes": wordgen.random_words(rng, 3000, 1, 3, alphabet=b"\x00\x01\x7f\x80\xfe\xff"),
+        "all_byte_values": wordgen.random_words(rng, 20000, 0, 12),
+        "max_len_64": wordgen.random_words(rng, 4000, 60, 64, alphabet=b"ab"),
+        "reverse_sorted": wordgen.Words.from_list(
+            [bytes([97 + (i // 676) % 26, 97 + (i // 26) % 26, 97 + i % 26]) for i in range(9000)][::-1]),
+        "n_1_mod_64": wordgen.random_words(rng, 64 * 37 + 1, 4, 4, alphabet=b"abc"),
+        "odd_n": wordgen.random_words(rng, 1023, 2, 2, alphabet=b"xyzXYZ"),
+        "huge_dup_bucket": wordgen.random_words(rng, 100_000, 3, 3, alphabet=b"ab"),
+        "one_bucket_big_distinct": wordgen.random_words(rng, 60_000, 8, 8),
+    }
+    for L in (4, 5, 7, 8, 9, 12, 13, 15, 16, 17, 24, 25, 31, 32, 33, 40, 48, 56, 63, 64):
+        cases[f"len_{L}"] = wordgen.random_words(rng, 700, L, L, alphabet=b"aAb\xff")
+    return cases
+
+
+EDGE = edge_cases()
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+def test_edge_cases(bs, ws, name):
+    w = EDGE[name]
+    ml = max(maxlen(w), 1)
+    expect = oracle.definition_sort(w.bytes, w.offsets)
+    if w.n <= 20000:
+        assert np.array_equal(oracle.bubble_sort(w.bytes, w.offsets, max_len=ml, threads=8), expect)
+    got = gpu_sort(bs, ws, w, ml)
+    assert np.array_equal(got, expect), name
+    got_small_tiles = gpu_sort(bs, ws, w, ml, tune=bs.tuning(128, 64))
+    assert np.array_equal(got_small_tiles, expect), name
+
+
+def test_empty_list(bs, ws):
+    w = wordgen.Words.from_list([])
+    b, o = bs.to_device(w.bytes, w.offsets)
+    counts, starts, order = bs.bucketize(b, o, 8, ws=ws)
+    bs.check_device_status(ws)
+    assert counts.cpu().numpy().tolist() == [0] * 9
+    assert starts.cpu().numpy().tolist() == [0] * 10
+    perm = bs.sort_buckets(b, o, counts, starts, order, 8, ws=ws)
+    assert perm.numel() == 0
+
+
+def test_repeat_is_deterministic(bs, ws):
+    """An LDS or cross-lane race would show as run-to-run differences."""
+    w = wordgen.single(2)
+    first = gpu_sort(bs, ws, w, 20, tune=bs.tuning(256, 64))
+    for _ in range(10):
+        assert np.array_equal(gpu_sort(bs, ws, w, 20, tune=bs.tuning(256, 64)), first)
+
+
+# ------------------------------------------------------------- 0-1 principle
+
+def zero_one_batch(seqs):
+    words = []
+    for s in seqs:
+        words.extend(b"1" if x else b"0" for x in s)
+    req = np.zeros(len(seqs) + 1, dtype=np.int64)
+    np.cumsum([len(s) for s in seqs], out=req[1:])
+    w = wordgen.Words.from_list(words)
+    return wordgen.Batch(w.bytes, w.offsets, req)
+
+
+def zero_one_expect(seqs):
+    out = []
+    for s in seqs:
+        s = np.asarray(s, dtype=np.int8)
+        out.append(np.concatenate([np.nonzero(s == 0)[0], np.nonzero(s == 1)[0]]))
+    return np.concatenate(out).astype(np.int32)
+
+
+def test_zero_one_exhaustive(bs, ws):
+    """Odd-even transposition sort is a comparator network, so it sorts all
+    inputs if it sorts all 0/1 inputs (Knuth, TAOCP 3, 5.3.4).  Every 0/1
+    sequence of length 1..14."""
+    seqs = []
+    for n in range(1, 15):
+        v = np.arange(2 ** n, dtype=np.int64)[:, None]
+        bits = (v >> np.arange(n - 1, -1, -1)) & 1
+        seqs.extend(list(bits.astype(np.int8)))
+    batch = zero_one_batch(seqs)
+    got = gpu_batch(bs, ws, batch, 1, tune=bs.tuning(128, 64))
+    assert np.array_equal(got, zero_one_expect(seqs))
+
+
+@pytest.mark.parametrize("T", [128, 256])
+def test_zero_one_merge_seams(bs, ws, T):
+    """Random 0/1 lists whose sizes sit on tile seams: the merge-split
+    network across tiles, ragged last tiles included."""
+    rng = np.random.default_rng(T)
+    seqs = []
+    for n in (T - 1, T, T + 1, 2 * T - 1, 2 * T, 2 * T + 1, 3 * T, 3 * T + 7, 7 * T + 5, 16 * T + 3):
+        for _ in range(40):
+            p = rng.random()
+            seqs.append((rng.random(n) < p).astype(np.int8))
+    batch = zero_one_batch(seqs)
+    got = gpu_batch(bs, ws, batch, 1, tune=bs.tuning(T, 64))
+    assert np.array_equal(got, zero_one_expect(seqs))
+
+
+# ------------------------------------------------------------- batches
+
+@pytest.fixture(scope="module")
+def batch_small():
+    return wordgen.batch(first=0, count=256)
+
+
+def test_batch_matches_oracle(bs, ws, batch_small):
+    expect, _ = oracle.bubble_sort_batch(batch_small.bytes, batch_small.offsets,
+                                         batch_small.req_start, 12, threads=16)
+    assert np.array_equal(gpu_batch(bs, ws, batch_small, 12), expect)
+
+
+def test_batch_equals_each_list_alone(bs, ws, batch_small):
+    got = gpu_batch(bs, ws, batch_small, 12)
+    for r in range(0, batch_small.R, 17):
+        w = batch_small.request(r)
+        alone = gpu_sort(bs, ws, w, 12)
+        a, b = batch_small.req_start[r], batch_small.req_start[r + 1]
+        assert np.array_equal(got[a:b], alone)
+
+
+def test_plain_per_bucket_form_equals_batched(bs, ws, batch_small):
+    sub = wordgen.Batch.concat([batch_small.request(r) for r in range(64)])
+    batched = gpu_batch(bs, ws, sub, 12)
+    plain = gpu_batch(bs, ws, sub, 12, tune=bs.tuning(0, 0, bs.FLAG_PER_BUCKET_LAUNCH))
+    assert np.array_equal(plain, batched)
+    expect = oracle.definition_sort_batch(sub.bytes, sub.offsets, sub.req_start, 16)
+    assert np.array_equal(batched, expect)
+
+
+def test_plan_replays_on_new_batches(bs, batch_small):
+    """A captured plan run twice in a row, the second time on a smaller batch
+    with other buffers; each result equals the oracle."""
+    a = wordgen.Batch.concat([batch_small.request(r) for r in range(0, 120)])
+    b = wordgen.Batch.concat([batch_small.request(r) for r in range(200, 240)])
+    cap_req = int(max(np.diff(a.req_start).max(), np.diff(b.req_start).max()))
+    plan = bs.Plan(a.total, a.R, cap_req, 12)
+    pws = bs.Workspace(plan.workspace_bytes)
+    for batch in (a, b, a):
+        bt, ot = bs.to_device(batch.bytes, batch.offsets)
+        rs = torch.from_numpy(batch.req_start).cuda()
+        perm = plan.execute(bt, ot, rs, batch.req_start, pws)
+        bs.check_device_status(pws)
+        expect = oracle.definition_sort_batch(batch.bytes, batch.offsets, batch.req_start, 16)
+        assert np.array_equal(perm.cpu().numpy(), expect)
+    plan.close()
+
+
+def test_full_batch_workload(bs, ws):
+    """The batching workload at full size (4,096 lists, ~31.8 M words), in
+    the launch configuration the benchmark times: every list against the
+    oracle's definition sort."""
+    batch = wordgen.batch()
+    got = gpu_batch(bs, ws, batch, 12)
+    expect = oracle.definition_sort_batch(batch.bytes, batch.offsets, batch.req_start, 16)
+    assert np.array_equal(got, expect)
+
+
+# ------------------------------------------------------------- faults
+
+def test_device_status_too_long(bs, ws):
+    w = wordgen.Words.from_list([b"ab", b"abcdefghij", b"a"])
+    b, o = bs.to_device(w.bytes, w.offsets)
+    bs.sort(b, o, 4, ws=ws)
+    assert bs.device_status(ws) == 2
+    assert bs.device_status(ws) == 0          # read clears it
+
+
+def test_device_status_bad_offsets(bs, ws):
+    buf = np.frombuffer(b"abcdefgh", np.uint8).copy()
+    off = np.array([0, 4, 2, 8, 20], np.int64)   # decreasing, and past n_bytes
+    b, o = bs.to_device(buf, off)
+    bs.sort(b, o, 16, ws=ws)
+    assert bs.device_status(ws) == 1
+
+
+def test_workspace_too_small(bs):
+    import ctypes
+    from paper_1407_6603_amd import _lib
+    w = wordgen.single(1)
+    b, o = bs.to_device(w.bytes, w.offsets)
+    tiny = bs.Workspace(256)
+    wd = _lib.Words(b.data_ptr(), b.numel(), o.data_ptr(), w.n, 12)
+    bk = _lib.Buckets(o.data_ptr(), o.data_ptr(), o.data_ptr())
+    rc = _lib.load().bsort_bucketize(ctypes.byref(wd), ctypes.byref(bk), tiny.ptr, 256, None)
+    assert rc == 4

@@ -119,6 +119,10 @@ MUTANTS = {
                           "starts[L + 1] = starts[L] + counts[L] - (L == 3);"),
     "reverse_index_tiebreak": ("return a < b ? -1 : (a > b ? 1 : 0);",
                                "return a > b ? -1 : (a < b ? 1 : 0);"),
+    "definition_ignores_length": ("if (la != lb) return la < lb ? -1 : 1;",
+                                  "if (la != lb) { int q = memcmp(c->bytes + c->offsets[a], "
+                                  "c->bytes + c->offsets[b], (size_t)(la < lb ? la : lb)); "
+                                  "if (q) return q; return la < lb ? -1 : 1; }"),
 }
 
 
