@@ -107,6 +107,10 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=8,
                     help="CPU baseline samples every k-th list of the batch")
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--tune-cache", default="", help="autotune cache file (default: package cache)")
+    ap.add_argument("--gen-workers", type=int, default=8,
+                    help="input generator processes; use 1 under a profiler that opens the "
+                         "GPU before main")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -116,7 +120,7 @@ def main():
 
     # inputs first (spawned worker processes, before the GPU is opened)
     t0 = time.time()
-    batch = wordgen.batch()
+    batch = wordgen.batch(workers=args.gen_workers)
     gen_s = time.time() - t0
     max_len = 12
     total = batch.total
@@ -133,40 +137,62 @@ def main():
 
     tile, mthreads, tuned_from = args.tile, args.merge_threads, "flags"
     if tile == 0 and mthreads == 0:
-        tile, mthreads, tuned_from = autotune.lookup(torch.cuda.get_device_name(0), "batch4096")
+        tile, mthreads, tuned_from = autotune.lookup(torch.cuda.get_device_name(0), "batch4096",
+                                                     args.tune_cache or autotune.CACHE)
 
     b_t, o_t = bs.to_device(batch.bytes, batch.offsets, dev)
     rs_t = torch.from_numpy(batch.req_start).to(dev)
     perm = torch.empty(total, dtype=torch.int32, device=dev)
-    cap_req = int(np.diff(batch.req_start).max())
-    tune = bs.tuning(tile, mthreads, bs.FLAG_STAGE_EVENTS)
-    plan = bs.Plan(total, batch.R, cap_req, max_len, tune)
-    ws = bs.Workspace(plan.workspace_bytes, dev)
+    tune = bs.tuning(tile, mthreads)
     stream = torch.cuda.current_stream()
+    ws = bs.Workspace(bs.workspace_bytes(total, max_len, batch.R), dev)
+    timer = bs.StageTimer(max_len, stream)
+
+    def step():
+        bs.sort_batch_staged(b_t, o_t, rs_t, batch.req_start, max_len, timer, tune, ws, out=perm)
 
     for _ in range(args.warmup):
-        plan.execute(b_t, o_t, rs_t, batch.req_start, ws, out=perm)
+        step()
     torch.cuda.synchronize()
     bs.check_device_status(ws)
 
-    # ---- timed region: K steps, per-step events, per-stage events in the graph
+    # ---- timed region: K steps; HIP events between stages on the launch stream
     stage_sum = {}
-    torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(args.steps):
-        plan.execute(b_t, o_t, rs_t, batch.req_start, ws, out=perm)
-        for k, v in plan.stage_ms().items():     # waits for this step
+        step()
+        for k, v in timer.ms().items():          # waits for this step
             stage_sum[k] = stage_sum.get(k, 0.0) + v
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
-    ms_per_step = ms_total / args.steps
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
     stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
     value = total / (ms_per_step / 1e3)
     bs.check_device_status(ws)
     got = perm.cpu().numpy()
+
+    # ---- the same batch through a captured graph plan (one graph launch per step)
+    cap_req = int(np.diff(batch.req_start).max())
+    plan = bs.Plan(total, batch.R, cap_req, max_len, tune)
+    gws = bs.Workspace(plan.workspace_bytes, dev)
+    gperm = torch.empty(total, dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        plan.execute(b_t, o_t, rs_t, batch.req_start, gws, out=gperm)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.execute(b_t, o_t, rs_t, batch.req_start, gws, out=gperm)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    bs.check_device_status(gws)
+    g_ms = ev0.elapsed_time(ev1) / args.steps
+    graph = {"value": total / (g_ms / 1e3), "unit": "words/s", "ms_per_step": g_ms,
+             "identical": bool(np.array_equal(gperm.cpu().numpy(), got))}
+    plan.close()
+    del gws, gperm
 
     # ---- the plain form: one launch per (list, length) sub-array and per phase
     plain = None
@@ -242,6 +268,7 @@ def main():
                    "global_batch": batch.R, "words": total, "max_len": max_len,
                    "tile_keys": tile or 1024, "merge_threads": mthreads or 256,
                    "tuning_source": tuned_from, "parallelism": "single GPU"},
+        "graph_plan": graph,
         "per_bucket_launch": plain,
         "batched_over_per_bucket": (value / plain["value"]) if plain else None,
         "stage_ms": stage_ms,
@@ -257,7 +284,6 @@ def main():
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(s + "\n")
-    plan.close()
 
 
 if __name__ == "__main__":

@@ -17,7 +17,9 @@
  *
  * Conventions for every entry point
  *   - Words are given as one byte buffer with no separators plus int64
- *     offsets: word i is bytes[offsets[i] .. offsets[i+1]-1].
+ *     offsets: word i is bytes[offsets[i] .. offsets[i+1]-1].  Only
+ *     bytes[offsets[0] .. offsets[n]-1] is read, so a caller holding a slice
+ *     of a longer byte stream may pass bytes = slice - offsets[0].
  *   - Every array argument named "device" is device memory on the current
  *     HIP device, allocated and owned by the caller; the library never frees
  *     or keeps it beyond the call's stream work.  Arrays named "host" are
@@ -96,11 +98,6 @@ typedef struct {
  * each tile sorted on its own. */
 #define BSORT_FLAG_TILES_ONLY 2
 
-/* Plans only: a HIP event is recorded between stages inside the captured
- * graph, so bsort_plan_stage_ms can report each stage's device time for the
- * last execute.  Other entry points ignore this flag. */
-#define BSORT_FLAG_STAGE_EVENTS 4
-
 /* Workspace bytes for up to total_words words in up to n_requests lists with
  * words of at most max_len bytes.  Returns 0 for invalid arguments. */
 size_t bsort_workspace_bytes(int64_t total_words, int32_t max_len, int32_t n_requests);
@@ -148,6 +145,25 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
                               void *ws, size_t ws_bytes, bsort_stream_t stream);
 
 /*
+ * Stage timing.  A batch sort runs these stages in order: "bucketize",
+ * "pack" (tile planning and key packing), one "oets_d<D>" tile-sort launch
+ * per record width D = 2 .. ceil(max_len/4)+1 (D = ceil(L/4)+1 for words of
+ * L bytes), and "merge_split".  bsort_stage_count(max_len) is their number
+ * and bsort_stage_name(max_len, i) the name of stage i (NULL if out of
+ * range).  bsort_sort_batch_staged is bsort_sort_batch that also records the
+ * caller's HIP events (hipEvent_t passed as void*) on the stream: events[0]
+ * before the first stage and events[i+1] after stage i, so
+ * hipEventElapsedTime(events[i], events[i+1]) is stage i's device time.
+ * n_events must be bsort_stage_count(b->max_len) + 1.  The per-bucket form
+ * cannot be staged.
+ */
+int bsort_stage_count(int32_t max_len);
+const char *bsort_stage_name(int32_t max_len, int i);
+bsort_status bsort_sort_batch_staged(const bsort_batch *b, int32_t *perm, const bsort_tuning *t,
+                                     void *ws, size_t ws_bytes, bsort_stream_t stream,
+                                     void *const *events, int n_events);
+
+/*
  * A captured batch: bsort_sort_batch's launches recorded once into a HIP
  * graph for batches within the given capacity, then replayed by
  * bsort_plan_execute with one graph launch (plus one small launch that
@@ -163,15 +179,6 @@ size_t bsort_plan_workspace_bytes(const bsort_plan *plan);
 bsort_status bsort_plan_execute(bsort_plan *plan, const bsort_batch *b, int32_t *perm,
                                 void *ws, size_t ws_bytes, bsort_stream_t stream);
 void bsort_plan_destroy(bsort_plan *plan);
-
-/* Stage timing of a plan built with BSORT_FLAG_STAGE_EVENTS: the number of
- * stages (0 without the flag), the name of stage i ("bucketize", "pack",
- * "oets_d<D>" per record width D = ceil(L/4)+1, "merge_split"), and the
- * device milliseconds of each stage in the plan's last execute, written to
- * ms[0..n-1].  bsort_plan_stage_ms waits for that execute to finish. */
-int bsort_plan_stage_count(const bsort_plan *plan);
-const char *bsort_plan_stage_name(const bsort_plan *plan, int i);
-bsort_status bsort_plan_stage_ms(bsort_plan *plan, float *ms, int n);
 
 /* Synchronises the stream and returns the status word a previous call left
  * in ws (BSORT_OK if none), then clears it. */

@@ -19,13 +19,12 @@ STATUS = {0: "BSORT_OK", 1: "BSORT_E_INVALID", 2: "BSORT_E_TOO_LONG", 3: "BSORT_
           4: "BSORT_E_WORKSPACE", 5: "BSORT_E_HIP", 6: "BSORT_E_CAPACITY"}
 FLAG_PER_BUCKET_LAUNCH = 1
 FLAG_TILES_ONLY = 2
-FLAG_STAGE_EVENTS = 4
 
 EXPORTS = [
     "bsort_workspace_bytes", "bsort_bucketize", "bsort_sort_buckets", "bsort_sort_batch",
     "bsort_plan_create", "bsort_plan_workspace_bytes", "bsort_plan_execute",
-    "bsort_plan_destroy", "bsort_plan_stage_count", "bsort_plan_stage_name",
-    "bsort_plan_stage_ms", "bsort_get_device_status", "bsort_status_string",
+    "bsort_plan_destroy", "bsort_stage_count", "bsort_stage_name", "bsort_sort_batch_staged",
+    "bsort_get_device_status", "bsort_status_string",
     "bsort_last_error", "bsort_version",
 ]
 
@@ -85,12 +84,13 @@ def load(path: str = LIB_PATH):
     L.bsort_plan_execute.argtypes = [P, ctypes.POINTER(Batch), P, P, sz, P]
     L.bsort_plan_destroy.argtypes = [P]
     L.bsort_plan_destroy.restype = None
-    L.bsort_plan_stage_count.argtypes = [P]
-    L.bsort_plan_stage_count.restype = ctypes.c_int
-    L.bsort_plan_stage_name.argtypes = [P, ctypes.c_int]
-    L.bsort_plan_stage_name.restype = ctypes.c_char_p
-    L.bsort_plan_stage_ms.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
-    L.bsort_plan_stage_ms.restype = ctypes.c_int
+    L.bsort_stage_count.argtypes = [i32]
+    L.bsort_stage_count.restype = ctypes.c_int
+    L.bsort_stage_name.argtypes = [i32, ctypes.c_int]
+    L.bsort_stage_name.restype = ctypes.c_char_p
+    L.bsort_sort_batch_staged.argtypes = [ctypes.POINTER(Batch), P, ctypes.POINTER(Tuning), P,
+                                          sz, P, ctypes.POINTER(P), ctypes.c_int]
+    L.bsort_sort_batch_staged.restype = ctypes.c_int
     L.bsort_get_device_status.argtypes = [P, P]
     for f in (L.bsort_bucketize, L.bsort_sort_buckets, L.bsort_sort_batch,
               L.bsort_plan_create, L.bsort_plan_execute, L.bsort_get_device_status):

@@ -18,7 +18,6 @@ Tuning = _lib.Tuning
 BsortError = _lib.BsortError
 FLAG_PER_BUCKET_LAUNCH = _lib.FLAG_PER_BUCKET_LAUNCH
 FLAG_TILES_ONLY = _lib.FLAG_TILES_ONLY
-FLAG_STAGE_EVENTS = _lib.FLAG_STAGE_EVENTS
 MAX_LEN = _lib.BSORT_MAX_LEN
 
 
@@ -139,8 +138,56 @@ def sort(bytes_t: torch.Tensor, offsets_t: torch.Tensor, max_len: int,
 def sort_batch(bytes_t: torch.Tensor, offsets_t: torch.Tensor, req_start_t: torch.Tensor,
                h_req_start: np.ndarray, max_len: int, tune: Optional[Tuning] = None,
                ws: Optional[Workspace] = None, stream=None,
-               out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Sort R lists stored back to back; perm holds list-local indices."""
+               out: Optional[torch.Tensor] = None, byte_origin: int = 0) -> torch.Tensor:
+    """Sort R lists stored back to back; perm holds list-local indices.
+
+    ``byte_origin``: bytes_t holds bytes [byte_origin, byte_origin +
+    numel) of the byte stream the offsets index (offsets[0] >= byte_origin)."""
+    _require_gpu()
+    _check_words(bytes_t, offsets_t)
+    h = np.ascontiguousarray(h_req_start, dtype=np.int64)
+    R = len(h) - 1
+    total = int(h[-1]) if R > 0 else 0
+    dev = offsets_t.device
+    perm = out if out is not None else torch.empty(total, dtype=torch.int32, device=dev)
+    ws = _ws_for(ws, workspace_bytes(total, max_len, max(R, 0)), dev)
+    bptr = (bytes_t.data_ptr() - int(byte_origin)) if bytes_t.numel() else None
+    b = _lib.Batch(bptr, int(byte_origin) + bytes_t.numel(), _ptr(offsets_t), _ptr(req_start_t),
+                   h.ctypes.data, R, max_len)
+    _lib.check(_lib.load().bsort_sort_batch(
+        ctypes.byref(b), _ptr(perm), ctypes.byref(tune) if tune is not None else None,
+        ws.ptr, ws.nbytes, _stream(stream)))
+    return perm
+
+
+def stage_names(max_len: int):
+    """Names of the stages of a batch sort, in launch order."""
+    L = _lib.load()
+    return [L.bsort_stage_name(max_len, i).decode() for i in range(L.bsort_stage_count(max_len))]
+
+
+class StageTimer:
+    """HIP events for bsort_sort_batch_staged, on one stream."""
+
+    def __init__(self, max_len: int, stream=None):
+        self.names = stage_names(max_len)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(len(self.names) + 1)]
+        for e in self.events:              # torch creates the HIP event on first record
+            e.record(self.stream)
+        self.handles = (ctypes.c_void_p * len(self.events))(*[e.cuda_event for e in self.events])
+
+    def ms(self):
+        """Per-stage device milliseconds of the last staged sort (waits for it)."""
+        self.events[-1].synchronize()
+        return {n: self.events[i].elapsed_time(self.events[i + 1])
+                for i, n in enumerate(self.names)}
+
+
+def sort_batch_staged(bytes_t, offsets_t, req_start_t, h_req_start, max_len: int,
+                      timer: StageTimer, tune: Optional[Tuning] = None,
+                      ws: Optional[Workspace] = None, out: Optional[torch.Tensor] = None):
+    """sort_batch that records timer's events between stages on timer.stream."""
     _require_gpu()
     _check_words(bytes_t, offsets_t)
     h = np.ascontiguousarray(h_req_start, dtype=np.int64)
@@ -151,9 +198,10 @@ def sort_batch(bytes_t: torch.Tensor, offsets_t: torch.Tensor, req_start_t: torc
     ws = _ws_for(ws, workspace_bytes(total, max_len, max(R, 0)), dev)
     b = _lib.Batch(_ptr(bytes_t), bytes_t.numel(), _ptr(offsets_t), _ptr(req_start_t),
                    h.ctypes.data, R, max_len)
-    _lib.check(_lib.load().bsort_sort_batch(
+    _lib.check(_lib.load().bsort_sort_batch_staged(
         ctypes.byref(b), _ptr(perm), ctypes.byref(tune) if tune is not None else None,
-        ws.ptr, ws.nbytes, _stream(stream)))
+        ws.ptr, ws.nbytes, ctypes.c_void_p(timer.stream.cuda_stream), timer.handles,
+        len(timer.events)))
     return perm
 
 
@@ -195,17 +243,6 @@ class Plan:
         _lib.check(self._lib.bsort_plan_execute(self._p, ctypes.byref(b), _ptr(perm), ws.ptr,
                                                 ws.nbytes, _stream(stream)))
         return perm
-
-    def stage_names(self):
-        n = self._lib.bsort_plan_stage_count(self._p)
-        return [self._lib.bsort_plan_stage_name(self._p, i).decode() for i in range(n)]
-
-    def stage_ms(self):
-        """Per-stage device milliseconds of the last execute (waits for it)."""
-        n = self._lib.bsort_plan_stage_count(self._p)
-        arr = (ctypes.c_float * max(n, 1))()
-        _lib.check(self._lib.bsort_plan_stage_ms(self._p, arr, n))
-        return dict(zip(self.stage_names(), [float(x) for x in arr[:n]]))
 
     def close(self):
         if self._p:

@@ -117,7 +117,7 @@ if __name__ == "__main__":
     ap.add_argument("--workload", default="batch4096")
     ap.add_argument("--out", default=CACHE)
     a = ap.parse_args()
-    batch = wordgen.batch()
+    batch = wordgen.batch(workers=8)       # before the GPU is opened
     b_t, o_t = bs.to_device(batch.bytes, batch.offsets)
     r_t = torch.from_numpy(batch.req_start).cuda()
     e = tune(b_t, o_t, r_t, batch.req_start, 12, a.workload, path=a.out)

@@ -88,8 +88,7 @@ bsort_status check_tuning(const bsort_tuning* t) {
     if (t->merge_threads != 0 &&
         (t->merge_threads < 64 || t->merge_threads > 1024 || t->merge_threads % 64))
         return fail(BSORT_E_INVALID, "merge_threads must be 0 or a multiple of 64 in [64, 1024]");
-    if (t->flags & ~(BSORT_FLAG_PER_BUCKET_LAUNCH | BSORT_FLAG_TILES_ONLY |
-                     BSORT_FLAG_STAGE_EVENTS))
+    if (t->flags & ~(BSORT_FLAG_PER_BUCKET_LAUNCH | BSORT_FLAG_TILES_ONLY))
         return fail(BSORT_E_INVALID, "unknown flag");
     return BSORT_OK;
 }
@@ -106,17 +105,20 @@ Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
     b.dmax = L.dmax;
     b.flags = t ? t->flags : 0;
     const int want = (t && t->tile_keys) ? t->tile_keys : kDefaultTile;
-    int tmin = 1 << 30, lds = 0;
+    const int budget = merge_lds_budget();
+    int tmin = 1 << 30, need = 0;
     for (int D = 2; D <= kMaxD; ++D) {
         int T = std::min(want, kWave * kmax_for(D));
+        while (T > kMinTile && D * 2 * T * 4 > budget) T >>= 1;   // both tiles fit in LDS
         b.tile_keys[D] = T;
         if (D <= L.dmax) {
             tmin = std::min(tmin, T);
-            lds = std::max(lds, D * 2 * T * 4);
+            need = std::max(need, D * 2 * T * 4);
         }
     }
     b.merge_threads = (t && t->merge_threads) ? t->merge_threads : kDefaultMergeThreads;
-    b.merge_lds = lds;
+    // twice the inputs when that fits: merged output staged in LDS, written coalesced
+    b.merge_lds = std::min(budget, 2 * need);
     int64_t pb = 0;
     if (L.dmax >= 2 && n_max >= 2) pb = (n_max + tmin - 1) / tmin;
     b.phase_bound = (int32_t)std::min<int64_t>(pb, L.phase_cap);
@@ -207,8 +209,6 @@ struct bsort_plan {
     Bounds bd;
     Job* job_dev;
     hipGraphExec_t exec;
-    std::vector<hipEvent_t> ev;          // stage boundaries (BSORT_FLAG_STAGE_EVENTS)
-    std::vector<std::string> stage_names;
 };
 
 extern "C" {
@@ -307,12 +307,38 @@ static Job batch_job(const Layout& L, char* ws, const Bounds& bd, const bsort_ba
     return j;
 }
 
-bsort_status bsort_sort_batch(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
-                              void* ws, size_t ws_bytes, bsort_stream_t stream) {
+int bsort_stage_count(int32_t max_len) {
+    if (max_len < 0 || max_len > BSORT_MAX_LEN) return 0;
+    const int dmax = max_len >= 1 ? dwords_for_len(max_len) : 1;
+    return 3 + (dmax >= 2 ? dmax - 1 : 0);
+}
+
+const char* bsort_stage_name(int32_t max_len, int i) {
+    static const char* kNames[] = {"bucketize", "pack", "oets_d2", "oets_d3", "oets_d4",
+                                   "oets_d5", "oets_d6", "oets_d7", "oets_d8", "oets_d9",
+                                   "oets_d10", "oets_d11", "oets_d12", "oets_d13", "oets_d14",
+                                   "oets_d15", "oets_d16", "oets_d17"};
+    const int n = bsort_stage_count(max_len);
+    if (i < 0 || i >= n) return nullptr;
+    if (i == n - 1) return "merge_split";
+    return kNames[i];
+}
+
+static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
+                                    void* ws, size_t ws_bytes, bsort_stream_t stream,
+                                    void* const* events, int n_events) {
     int64_t total, n_max;
     bsort_status st = check_batch(b, perm, total, n_max);
     if (st != BSORT_OK) return st;
     if ((st = check_tuning(t)) != BSORT_OK) return st;
+    if (events) {
+        if (n_events != bsort_stage_count(b->max_len) + 1)
+            return fail(BSORT_E_INVALID, "n_events must be bsort_stage_count(max_len) + 1");
+        for (int i = 0; i < n_events; ++i)
+            if (!events[i]) return fail(BSORT_E_INVALID, "an event is NULL");
+        if (t && (t->flags & BSORT_FLAG_PER_BUCKET_LAUNCH))
+            return fail(BSORT_E_INVALID, "the per-bucket form cannot be staged");
+    }
     Layout L;
     make_layout(total, b->n_requests, b->max_len, L);
     if ((st = check_ws(L, ws, ws_bytes)) != BSORT_OK) return st;
@@ -323,10 +349,35 @@ bsort_status bsort_sort_batch(const bsort_batch* b, int32_t* perm, const bsort_t
     Bounds bd = make_bounds(L, total, b->n_requests, n_max, t);
     Job* jd = (Job*)((char*)ws + L.job);
     Job j = batch_job(L, (char*)ws, bd, b, total, perm);
+    int k = 0;
+    auto mark = [&]() -> hipError_t {
+        return events ? hipEventRecord((hipEvent_t)events[k++], s) : hipSuccess;
+    };
     HIP_TRY(launch_set_job(j, jd, s));
+    HIP_TRY(mark());
     HIP_TRY(launch_bucketize(jd, bd, s));
-    HIP_TRY(launch_sort(jd, bd, s));
+    HIP_TRY(mark());
+    HIP_TRY(launch_sort_prep(jd, bd, s));
+    for (int D = 2; D <= bd.dmax && D <= kMaxD; ++D) {
+        HIP_TRY(mark());
+        HIP_TRY(launch_oets_tiles_one(jd, bd, D, s));
+    }
+    HIP_TRY(mark());
+    HIP_TRY(launch_merges(jd, bd, s));
+    HIP_TRY(mark());
     return BSORT_OK;
+}
+
+bsort_status bsort_sort_batch(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
+                              void* ws, size_t ws_bytes, bsort_stream_t stream) {
+    return sort_batch_impl(b, perm, t, ws, ws_bytes, stream, nullptr, 0);
+}
+
+bsort_status bsort_sort_batch_staged(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
+                                     void* ws, size_t ws_bytes, bsort_stream_t stream,
+                                     void* const* events, int n_events) {
+    if (!events) return fail(BSORT_E_INVALID, "events is NULL");
+    return sort_batch_impl(b, perm, t, ws, ws_bytes, stream, events, n_events);
 }
 
 bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap_requests,
@@ -362,45 +413,19 @@ bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap
         return fail(BSORT_E_NO_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
     e = hipSuccess;
-    const bool stage_events = t && (t->flags & BSORT_FLAG_STAGE_EVENTS);
-    if (stage_events) {
-        p->stage_names.push_back("bucketize");
-        p->stage_names.push_back("pack");
-        for (int D = 2; D <= p->bd.dmax && D <= kMaxD; ++D)
-            p->stage_names.push_back("oets_d" + std::to_string(D));
-        p->stage_names.push_back("merge_split");
-        p->ev.assign(p->stage_names.size() + 1, nullptr);
-        for (auto& ev : p->ev)
-            if (e == hipSuccess) e = hipEventCreate(&ev);
-    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        int k = 0;
-        auto mark = [&]() -> hipError_t {
-            return stage_events ? hipEventRecord(p->ev[k++], cs) : hipSuccess;
-        };
-        hipError_t e1 = mark();
-        if (e1 == hipSuccess) e1 = launch_bucketize(p->job_dev, p->bd, cs);
-        if (e1 == hipSuccess) e1 = mark();
-        if (e1 == hipSuccess) e1 = launch_sort_prep(p->job_dev, p->bd, cs);
-        for (int D = 2; D <= p->bd.dmax && D <= kMaxD && e1 == hipSuccess; ++D) {
-            e1 = mark();
-            if (e1 == hipSuccess) e1 = launch_oets_tiles_one(p->job_dev, p->bd, D, cs);
-        }
-        if (e1 == hipSuccess) e1 = mark();
-        if (e1 == hipSuccess) e1 = launch_merges(p->job_dev, p->bd, cs);
-        if (e1 == hipSuccess) e1 = mark();
+        hipError_t e1 = launch_bucketize(p->job_dev, p->bd, cs);
+        if (e1 == hipSuccess) e1 = launch_sort(p->job_dev, p->bd, cs);
         e = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = e1;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
-    if (graph) hipGraphDestroy(graph);
-    if (cs) hipStreamDestroy(cs);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
-        for (auto ev : p->ev)
-            if (ev) hipEventDestroy(ev);
-        hipFree(p->job_dev);
+        (void)hipFree(p->job_dev);
         delete p;
         return fail(BSORT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     }
@@ -428,31 +453,10 @@ bsort_status bsort_plan_execute(bsort_plan* p, const bsort_batch* b, int32_t* pe
     return BSORT_OK;
 }
 
-int bsort_plan_stage_count(const bsort_plan* p) {
-    return p ? (int)p->stage_names.size() : 0;
-}
-
-const char* bsort_plan_stage_name(const bsort_plan* p, int i) {
-    if (!p || i < 0 || i >= (int)p->stage_names.size()) return nullptr;
-    return p->stage_names[i].c_str();
-}
-
-bsort_status bsort_plan_stage_ms(bsort_plan* p, float* ms, int n) {
-    if (!p || !ms) return fail(BSORT_E_INVALID, "plan or ms is NULL");
-    if (p->stage_names.empty()) return fail(BSORT_E_INVALID, "plan built without stage events");
-    if (n < (int)p->stage_names.size()) return fail(BSORT_E_INVALID, "ms too short");
-    HIP_TRY(hipEventSynchronize(p->ev.back()));
-    for (size_t i = 0; i < p->stage_names.size(); ++i)
-        HIP_TRY(hipEventElapsedTime(&ms[i], p->ev[i], p->ev[i + 1]));
-    return BSORT_OK;
-}
-
 void bsort_plan_destroy(bsort_plan* p) {
     if (!p) return;
-    for (auto ev : p->ev)
-        if (ev) hipEventDestroy(ev);
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->job_dev) hipFree(p->job_dev);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->job_dev) (void)hipFree(p->job_dev);
     delete p;
 }
 
@@ -528,6 +532,8 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
         j.perm = perm + h[r];
         j.keys = (uint64_t*)(ws + L.keys) + (int64_t)wmax * h[r];
         j.key_off = (int64_t*)(ws + L.key_off) + (int64_t)r * ml1;
+        // each list keeps its own chunk map: its pack runs after every list's bucketize
+        j.chunk_begin = (int64_t*)((char*)&jobs[r] + offsetof(Job, cb_inline));
         j.chunk_cap = Lr.chunk_cap;
         if (r > 0) j.flags |= kJobKeepStatus;
         HIP_TRY(launch_set_job(j, &jobs[r], s));
@@ -582,8 +588,9 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
             m.T = T;
             m.a = 0;
             m.p = nt;
-            m.pad = 0;
-            const int lds = D * 2 * T * 4;
+            m.s = 0;
+            m.pair_base = 0;
+            const int lds = bd0.merge_lds;
             for (int ph = 0; ph < nt; ++ph) {
                 const int npairs = (nt - (ph & 1)) / 2;
                 HIP_TRY(launch_merge_one_bucket(&jobs[r], m, npairs, ph, bd0.merge_threads, lds, s));

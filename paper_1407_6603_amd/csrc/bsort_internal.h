@@ -32,9 +32,10 @@ constexpr int kChunkRounds = 16;
 constexpr int kChunk = kWave * kChunkRounds;   // words per bucketize chunk
 constexpr int kTileWavesPerBlock = 4;
 constexpr int kMinTile = 128;             // 64 lanes x 2 records
-constexpr int kMaxPhaseCap = 1 << 22;
 constexpr int kFlagTilesOnly = 2;         // same value as BSORT_FLAG_TILES_ONLY
 constexpr int kJobKeepStatus = 1 << 8;    // Job.flags: leave the status word as it is
+constexpr int kMergeGrid = 1024;          // workgroups of the persistent merge kernel
+constexpr int kMaxPhaseCap = 1 << 22;
 
 // device status bits (workspace status word)
 enum : uint32_t {
@@ -42,7 +43,11 @@ enum : uint32_t {
     ST_TOO_LONG = 2u,
     ST_BAD_REQ = 4u,
     ST_OVERFLOW = 8u,      // an internal list bound was exceeded (a library bug)
+    ST_STALLED = 16u,      // a bounded wait in the merge scheduler gave up (a library bug)
 };
+
+// queue control words (Job.qctl)
+enum { Q_HEAD = 0, Q_TAIL = 1, Q_TOTAL = 2, Q_ABORT = 3, Q_ARR = 4, Q_WORDS = 8 };
 
 // records per lane limit by key width: D * K <= 128 VGPRs of record state
 __host__ __device__ constexpr int kmax_for(int D) {
@@ -50,6 +55,11 @@ __host__ __device__ constexpr int kmax_for(int D) {
 }
 __host__ __device__ constexpr int dwords_for_len(int L) { return (L + 3) / 4 + 1; }
 __host__ __device__ constexpr int lanes_for_len(int L) { return (L + 7) / 8; }
+// merge-split work items of a sub-array of p tiles: ceil(p/2) even phases of
+// floor(p/2) pairs and floor(p/2) odd phases of floor((p-1)/2) pairs
+__host__ __device__ constexpr int64_t merge_items_for(int64_t p) {
+    return ((p + 1) / 2) * (p / 2) + (p / 2) * ((p - 1) / 2);
+}
 
 struct TileDesc {            // one odd-even transposition tile
     int64_t pos0;            // global position of the bucket's first word
@@ -60,15 +70,16 @@ struct TileDesc {            // one odd-even transposition tile
     int32_t L;               // word length
 };
 
-struct MergeItem {           // one merge-split of tiles a and a+1 of a bucket
+struct MergeItem {           // merge-split of tiles a and a+1 of a bucket at phase s
     int64_t pos0;
     int64_t key_off;
+    int64_t pair_base;       // arrival counters of this bucket's pairs start here
     int32_t n_b;
     int32_t L;
     int32_t T;               // tile size of this bucket
     int32_t a;               // lower tile
     int32_t p;               // tiles in the bucket
-    int32_t pad;
+    int32_t s;               // phase
 };
 
 struct Job {
@@ -98,12 +109,20 @@ struct Job {
     int64_t tile_cap[kNumD];
     int32_t tile_keys[kNumD];    // tile size per D
     int32_t* tile_count;         // [kNumD]
-    MergeItem* mlist[2];         // double-buffered phase lists
+    // per-phase merge-split lists (phase s reads mlist[s&1], queues into the other)
+    MergeItem* mlist[2];
     int64_t merge_cap;
     int32_t* mcount;             // [phase_cap + 1]
     int32_t phase_cap;
     int32_t pad0;
+    // dataflow merge-split scheduler
+    MergeItem* ring;             // [ring_cap] ready items
+    int64_t* ring_seq;           // [ring_cap] 2t+1: holds ticket t; 2t+2: ticket t consumed
+    int64_t ring_cap;
+    int32_t* arr;                // [ring_cap] arrivals per (bucket, pair) slot
+    int64_t* qctl;               // [Q_WORDS] head, tail, total, abort, pair-slot allocator
     int64_t rs_inline[2];        // req_start storage for single-list calls
+    int64_t cb_inline[2];        // chunk_begin storage for the plain form's per-list jobs
 };
 
 // ---------------------------------------------------------------- helpers
@@ -120,6 +139,40 @@ __device__ __forceinline__ int upper_index(const int64_t* a, int n, int64_t x) {
         if (a[mid] <= x) lo = mid; else hi = mid;
     }
     return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T u = __shfl_up(v, d, kWave);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// list r's word range [a, b), clamped into [0, total]
+__device__ __forceinline__ void req_bounds(const Job* J, int r, int64_t& a, int64_t& b) {
+    int64_t x = J->req_start[r], y = J->req_start[r + 1];
+    x = x < 0 ? 0 : (x > J->total ? J->total : x);
+    y = y < x ? x : (y > J->total ? J->total : y);
+    a = x;
+    b = y;
+}
+
+// Chunk c -> list r and its global word range [gs, ge).  Chunks never
+// straddle lists; chunk_begin is the running sum of ceil(n_r / kChunk).
+__device__ __forceinline__ bool chunk_range(const Job* J, int64_t c, int& r, int64_t& a,
+                                            int64_t& b, int64_t& gs, int64_t& ge) {
+    const int R = J->R;
+    int64_t nch = J->chunk_begin[R];
+    if (nch > J->chunk_cap) nch = J->chunk_cap;
+    if (c >= nch) return false;
+    r = upper_index(J->chunk_begin, R, c);
+    req_bounds(J, r, a, b);
+    gs = a + (c - J->chunk_begin[r]) * kChunk;
+    ge = gs + kChunk < b ? gs + kChunk : b;
+    return true;
 }
 
 // Lexicographic a > b over D dwords, a[0] most significant.  Adjacent dwords
@@ -164,8 +217,9 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
     int32_t ml1;
     int64_t chunk_cap;
     int64_t tile_cap;        // tile list capacity per record width
+    int64_t ring_cap;
     int32_t dmax;            // widest record in use
-    int32_t phase_bound;     // merge-split phases to launch
+    int32_t phase_bound;     // merge-split phase launches
     int32_t merge_threads;
     int32_t merge_lds;       // dynamic LDS bytes per merge workgroup
     int32_t tile_keys[kNumD];
@@ -174,17 +228,19 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
 
 hipError_t launch_set_job(const Job& j, Job* dst, hipStream_t s);
 hipError_t launch_bucketize(const Job* J, const Bounds& b, hipStream_t s);
+hipError_t launch_chunk_plan(const Job* J, bool clear_status, hipStream_t s);
 hipError_t launch_sort(const Job* J, const Bounds& b, hipStream_t s);
+hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s);
+hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
+hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s);
+hipError_t launch_merge_phase(const Job* J, const Bounds& b, int phase, hipStream_t s);
 // plain per-bucket form pieces
 hipError_t launch_pack(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_tile_one_bucket(const Job* J, int D, const TileDesc& first, int ntiles,
                                   int T, bool write_keys, hipStream_t s);
 hipError_t launch_merge_one_bucket(const Job* J, const MergeItem& item0, int npairs,
                                    int phase, int merge_threads, int lds, hipStream_t s);
-hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s);
-hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
-hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s);
-hipError_t launch_merge_phase(const Job* J, const Bounds& b, int phase, hipStream_t s);
-
+// dynamic LDS a merge workgroup may use on this device (bytes)
+int merge_lds_budget();
 
 }  // namespace bsort

@@ -2,7 +2,9 @@
 // and its sub-arrays filled in input order (Section II pre-processing phase
 // 2; Section III approach two's count array l[]).
 //
-//   k_chunk_plan    one workgroup: chunks per list, their running sum
+//   k_chunk_plan    one workgroup: chunks per list, their running sum (the
+//                   sort side re-runs it: its chunk map must not depend on
+//                   what an earlier call left in the workspace)
 //   k_chunk_hist    one wave per chunk of 1024 words: length histogram
 //   k_chunk_scan    one wave per (list, length): exclusive scan over chunks
 //   k_bucket_starts one wave per list: starts = exclusive scan of counts
@@ -13,24 +15,6 @@
 #include "bsort_internal.h"
 
 namespace bsort {
-
-template <typename T>
-__device__ __forceinline__ T wave_incl_scan(T v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T u = __shfl_up(v, d, kWave);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
-__device__ __forceinline__ void req_bounds(const Job* J, int r, int64_t& a, int64_t& b) {
-    int64_t x = J->req_start[r], y = J->req_start[r + 1];
-    x = x < 0 ? 0 : (x > J->total ? J->total : x);
-    y = y < x ? x : (y > J->total ? J->total : y);
-    a = x;
-    b = y;
-}
 
 // length of global word g, or -1 (with a status bit) if it is malformed
 __device__ __forceinline__ int word_len(const Job* J, int64_t g, uint32_t& bad) {
@@ -50,13 +34,13 @@ __global__ void k_set_job(Job j, Job* dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = j;
 }
 
-__global__ __launch_bounds__(1024) void k_chunk_plan(const Job* __restrict__ J) {
+__global__ __launch_bounds__(1024) void k_chunk_plan(const Job* __restrict__ J, int clear_status) {
     __shared__ int64_t wsum[16];
     __shared__ int64_t carry;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int R = J->R;
     if (tid == 0) {
-        if (!(J->flags & kJobKeepStatus)) *J->status = 0u;
+        if (clear_status && !(J->flags & kJobKeepStatus)) *J->status = 0u;
         carry = 0;
         if (J->req_start[0] != 0 || J->req_start[R] != J->total) set_status(J, ST_BAD_REQ);
     }
@@ -85,20 +69,6 @@ __global__ __launch_bounds__(1024) void k_chunk_plan(const Job* __restrict__ J) 
         if (tid == 0) carry += wsum[15];
         __syncthreads();
     }
-}
-
-// chunk c -> list r, and its global word range [gs, ge)
-__device__ __forceinline__ bool chunk_range(const Job* J, int64_t c, int& r, int64_t& a,
-                                            int64_t& b, int64_t& gs, int64_t& ge) {
-    const int R = J->R;
-    int64_t nch = J->chunk_begin[R];
-    if (nch > J->chunk_cap) nch = J->chunk_cap;
-    if (c >= nch) return false;
-    r = upper_index(J->chunk_begin, R, c);
-    req_bounds(J, r, a, b);
-    gs = a + (c - J->chunk_begin[r]) * kChunk;
-    ge = gs + kChunk < b ? gs + kChunk : b;
-    return true;
 }
 
 __global__ __launch_bounds__(256) void k_chunk_hist(const Job* __restrict__ J) {
@@ -215,8 +185,13 @@ hipError_t launch_set_job(const Job& j, Job* dst, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_chunk_plan(const Job* J, bool clear_status, hipStream_t s) {
+    k_chunk_plan<<<1, 1024, 0, s>>>(J, clear_status ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_bucketize(const Job* J, const Bounds& b, hipStream_t s) {
-    k_chunk_plan<<<1, 1024, 0, s>>>(J);
+    k_chunk_plan<<<1, 1024, 0, s>>>(J, 1);
     k_chunk_hist<<<grid_for(b.chunk_cap, kTileWavesPerBlock), 256, 0, s>>>(J);
     k_chunk_scan<<<grid_for((int64_t)b.R * b.ml1, kTileWavesPerBlock), 256, 0, s>>>(J);
     k_bucket_starts<<<grid_for(b.R, kTileWavesPerBlock), 256, 0, s>>>(J);

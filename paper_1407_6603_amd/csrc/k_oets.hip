@@ -49,6 +49,101 @@ __device__ __forceinline__ void cross_lane_odd(uint32_t (&first)[D], uint32_t (&
     }
 }
 
+// ---- exact double min/max compare-exchange for records of two dwords (L <= 4)
+//
+// A record (key32, index) with index < 2^31 is the integer v = key32*2^31 +
+// index.  With key32 < 0xFFC00000, v + 2^52 lies in [2^52, 0x7FEFFFFFFFFFFFFF],
+// the bit patterns of positive normal doubles, whose order as doubles is the
+// order of the patterns as unsigned integers; IEEE min and max return one of
+// their operands unchanged.  So v_min_f64/v_max_f64 on these patterns are an
+// exact compare-exchange of the records.  +inf pads the tile and 0.0 is below
+// every record, so the cross-lane exchange needs no lane masks.
+constexpr uint32_t kF64KeyLimit = 0xFFC00000u;
+constexpr uint64_t kF64Bias = 1ull << 52;
+constexpr uint64_t kF64Inf = 0x7FF0000000000000ull;
+
+__device__ __forceinline__ double dmin(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double dmax(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double dpp_f64(double x, int ctrl_is_shl, uint64_t old_bits) {
+    const uint64_t v = (uint64_t)__double_as_longlong(x);
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const int olo = (int)(uint32_t)old_bits, ohi = (int)(uint32_t)(old_bits >> 32);
+    int rlo, rhi;
+    if (ctrl_is_shl) {
+        rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x130, 0xF, 0xF, false);
+        rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x130, 0xF, 0xF, false);
+    } else {
+        rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x138, 0xF, 0xF, false);
+        rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x138, 0xF, 0xF, false);
+    }
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)rhi << 32) | (uint32_t)rlo));
+}
+
+template <int K>
+__device__ __forceinline__ void phases_f64(uint32_t (&r)[K][2], int nph) {
+    double x[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint64_t v = r[k][0] == 0xFFFFFFFFu && r[k][1] == 0xFFFFFFFFu
+                               ? kF64Inf
+                               : (((uint64_t)r[k][0] << 31) | r[k][1]) + kF64Bias;
+        x[k] = __longlong_as_double((long long)v);
+    }
+    for (int ph = 0; ph < nph; ph += 2) {
+#pragma unroll
+        for (int k = 0; k + 1 < K; k += 2) {
+            const double lo = dmin(x[k], x[k + 1]), hi = dmax(x[k], x[k + 1]);
+            x[k] = lo;
+            x[k + 1] = hi;
+        }
+        if (ph + 1 < nph) {
+            const double rf = dpp_f64(x[0], 1, kF64Inf);    // right neighbour's first
+            const double ll = dpp_f64(x[K - 1], 0, 0);      // left neighbour's last
+#pragma unroll
+            for (int k = 1; k + 1 <= K - 2; k += 2) {
+                const double lo = dmin(x[k], x[k + 1]), hi = dmax(x[k], x[k + 1]);
+                x[k] = lo;
+                x[k + 1] = hi;
+            }
+            x[K - 1] = dmin(x[K - 1], rf);
+            x[0] = dmax(ll, x[0]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint64_t v = (uint64_t)__double_as_longlong(x[k]);
+        if (v == kF64Inf) {
+            r[k][0] = 0xFFFFFFFFu;
+            r[k][1] = 0xFFFFFFFFu;
+        } else {
+            const uint64_t u = v - kF64Bias;
+            r[k][0] = (uint32_t)(u >> 31);
+            r[k][1] = (uint32_t)(u & 0x7FFFFFFFu);
+        }
+    }
+}
+
+template <int D, int K>
+__device__ __forceinline__ void phases_int(uint32_t (&r)[K][D], int nph, int lane) {
+    for (int ph = 0; ph < nph; ph += 2) {
+#pragma unroll
+        for (int k = 0; k + 1 < K; k += 2) cex<D>(r[k], r[k + 1]);          // even phase
+        if (ph + 1 < nph) {                                                  // odd phase
+#pragma unroll
+            for (int k = 1; k + 1 <= K - 2; k += 2) cex<D>(r[k], r[k + 1]);
+            cross_lane_odd<D>(r[0], r[K - 1], lane);
+        }
+    }
+}
+
 template <int D, int K>
 __device__ __forceinline__ void oets_tile(const Job* __restrict__ J, const TileDesc& t,
                                           bool write_keys, int lane) {
@@ -79,14 +174,15 @@ __device__ __forceinline__ void oets_tile(const Job* __restrict__ J, const TileD
     }
 
     const int nph = t.n;
-    for (int ph = 0; ph < nph; ph += 2) {
+    if constexpr (D == 2) {
+        bool ok = true;
 #pragma unroll
-        for (int k = 0; k + 1 < K; k += 2) cex<D>(r[k], r[k + 1]);          // even phase
-        if (ph + 1 < nph) {                                                  // odd phase
-#pragma unroll
-            for (int k = 1; k + 1 <= K - 2; k += 2) cex<D>(r[k], r[k + 1]);
-            cross_lane_odd<D>(r[0], r[K - 1], lane);
-        }
+        for (int k = 0; k < K; ++k)
+            if (jbase + k < jend && r[k][0] >= kF64KeyLimit) ok = false;
+        if (__all(ok)) phases_f64<K>(r, nph);
+        else phases_int<D, K>(r, nph, lane);
+    } else {
+        phases_int<D, K>(r, nph, lane);
     }
 
 #pragma unroll

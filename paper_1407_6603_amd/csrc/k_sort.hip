@@ -1,99 +1,104 @@
 // Sort side of the path, except the tile sort itself (k_oets.hip):
 //
 //   k_sort_init   zero the work-list counters
-//   k_tile_plan   one wave per list: key-lane offsets of its sub-arrays, the
-//                 odd-even transposition tiles of each sub-array, and the
-//                 first merge-split phase's work items
-//   k_pack        one thread per word: big-endian uint64 key lanes (the
-//                 paper's fixed-width word slots, Section III approach two)
-//                 and the initial index payload
+//   k_tile_plan   one wave per list, four lists per workgroup: key-lane
+//                 offsets of the list's sub-arrays, its odd-even
+//                 transposition tiles and the first merge-split phase's work
+//                 items; list slots are claimed with one global atomic per
+//                 workgroup and record width
+//   k_pack        one wave per 1,024-word chunk: big-endian uint64 key lanes
+//                 (the paper's fixed-width word slots, Section III approach
+//                 two) and the initial index payload
 //   k_merge_phase one workgroup per (sub-array, tile pair) of one phase of
 //                 the block odd-even merge-split (Baudet and Stevenson,
 //                 1978): tiles a and a+1 of a sub-array, both sorted, are
 //                 merged; the lower keeps the smaller half.  p phases sort a
-//                 sub-array of p tiles.  Each item also queues its
-//                 successors of the next phase.
+//                 sub-array of p tiles.  Each item queues its successors of
+//                 the next phase.
 #include "bsort_internal.h"
 
 namespace bsort {
 
-template <typename T>
-__device__ __forceinline__ T wave_incl_scan2(T v, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T u = __shfl_up(v, d, kWave);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
-__device__ __forceinline__ void req_bounds2(const Job* J, int r, int64_t& a, int64_t& b) {
-    int64_t x = J->req_start[r], y = J->req_start[r + 1];
-    x = x < 0 ? 0 : (x > J->total ? J->total : x);
-    y = y < x ? x : (y > J->total ? J->total : y);
-    a = x;
-    b = y;
-}
-
 __global__ __launch_bounds__(256) void k_sort_init(const Job* __restrict__ J) {
-    for (int i = threadIdx.x; i < kNumD; i += blockDim.x) J->tile_count[i] = 0;
-    for (int i = threadIdx.x; i <= J->phase_cap; i += blockDim.x) J->mcount[i] = 0;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    if (i0 < kNumD) J->tile_count[i0] = 0;
+    for (int64_t i = i0; i <= J->phase_cap; i += step) J->mcount[i] = 0;
 }
 
+// one wave per list; the workgroup's four waves share one global claim per
+// record width D and one for the first merge phase
 __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     __shared__ int64_t kos[kTileWavesPerBlock][kMaxLen + 1];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ int blk_tiles[kNumD];
+    __shared__ int64_t blk_tile_base[kNumD];
+    __shared__ int blk_items;
+    __shared__ int64_t blk_item_base;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid < kNumD) blk_tiles[tid] = 0;
+    if (tid == 0) blk_items = 0;
+    __syncthreads();
+
     const int r = blockIdx.x * kTileWavesPerBlock + wv;
-    if (r >= J->R) return;
-    int64_t a, b;
-    req_bounds2(J, r, a, b);
+    const bool active = r < J->R;
     const int ml1 = J->ml1;
     const int wmax = lanes_for_len(J->max_len);
-    const int32_t* cnt = J->counts + (int64_t)r * ml1;
-    const int32_t* st = J->starts + (int64_t)r * (ml1 + 1);
     const bool tiles_only = (J->flags & kFlagTilesOnly) != 0;
+    int64_t a = 0, b = 0;
+    if (active) req_bounds(J, r, a, b);
+    const int32_t* cnt = J->counts + (int64_t)(active ? r : 0) * ml1;
+    const int32_t* st = J->starts + (int64_t)(active ? r : 0) * (ml1 + 1);
 
-    // uint64 offset of each sub-array's lane 0: exclusive scan of W(L)*n_L
-    int64_t run = (int64_t)wmax * a;
-    for (int base = 0; base < ml1; base += kWave) {
-        const int L = base + lane;
-        int nb = L < ml1 ? cnt[L] : 0;
-        if (nb < 0) nb = 0;
-        const int64_t v = (int64_t)lanes_for_len(L) * nb;
-        const int64_t incl = wave_incl_scan2(v, lane);
-        if (L < ml1) {
+    // per length L = lane + 64*k (k = 0, 1): tiles, tile slot, merge slot
+    int nt[2] = {0, 0}, tslot[2] = {0, 0}, islot[2] = {0, 0};
+    if (active) {
+        int64_t run = (int64_t)wmax * a;    // uint64 offset of each sub-array's lane 0
+        for (int k = 0; k < 2; ++k) {
+            const int L = lane + kWave * k;
+            if (kWave * k >= ml1) break;    // uniform
+            int nb = L < ml1 ? cnt[L] : 0;
+            if (nb < 0) nb = 0;
+            const int64_t v = (int64_t)lanes_for_len(L) * nb;
+            const int64_t incl = wave_incl_scan(v, lane);
             const int64_t ko = run + incl - v;
+            run += __shfl(incl, kWave - 1, kWave);
+            if (L >= ml1) continue;
             kos[wv][L] = ko;
             J->key_off[(int64_t)r * ml1 + L] = ko;
+            if (L == 0 || nb < 2) continue;  // 0 or 1 word: already in order
+            if (st[L] < 0 || (int64_t)st[L] + nb > b - a ||
+                ko + (int64_t)lanes_for_len(L) * nb > (int64_t)wmax * b) {
+                set_status(J, ST_BAD_REQ);  // counts/starts inconsistent with the list
+                continue;
+            }
+            const int D = dwords_for_len(L);
+            const int T = J->tile_keys[D];
+            nt[k] = (nb + T - 1) / T;
+            tslot[k] = atomicAdd(&blk_tiles[D], nt[k]);
+            if (nt[k] >= 2 && !tiles_only) islot[k] = atomicAdd(&blk_items, nt[k] / 2);
         }
-        run += __shfl(incl, kWave - 1, kWave);
     }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+    if (tid < kNumD && blk_tiles[tid] > 0)
+        blk_tile_base[tid] = atomicAdd(&J->tile_count[tid], blk_tiles[tid]);
+    if (tid == kNumD && blk_items > 0) blk_item_base = atomicAdd(&J->mcount[0], blk_items);
+    __syncthreads();
+    if (!active) return;
 
-    for (int L = 1; L < ml1; ++L) {                 // uniform over the wave
+    for (int k = 0; k < 2; ++k) {
+        if (nt[k] == 0) continue;
+        const int L = lane + kWave * k;
         const int nb = cnt[L];
-        if (nb < 2) continue;                        // 0 or 1 word: already in order
-        if (st[L] < 0 || (int64_t)st[L] + nb > b - a) {
-            if (lane == 0) set_status(J, ST_BAD_REQ);
-            continue;
-        }
-        const int64_t ko = kos[wv][L];
-        if (ko + (int64_t)lanes_for_len(L) * nb > (int64_t)wmax * b) {   // counts inconsistent
-            if (lane == 0) set_status(J, ST_BAD_REQ);
-            continue;
-        }
         const int D = dwords_for_len(L);
         const int T = J->tile_keys[D];
-        const int nt = (nb + T - 1) / T;
-        int slot = 0;
-        if (lane == 0) slot = atomicAdd(&J->tile_count[D], nt);
-        slot = __shfl(slot, 0, kWave);
-        if ((int64_t)slot + nt > J->tile_cap[D]) {
-            if (lane == 0) set_status(J, ST_OVERFLOW);
+        const int64_t pos0 = a + st[L];
+        const int64_t ko = kos[wv][L];
+        const int64_t base = blk_tile_base[D] + tslot[k];
+        if (base + nt[k] > J->tile_cap[D]) {
+            set_status(J, ST_OVERFLOW);
             continue;
         }
-        const int64_t pos0 = a + st[L];
-        for (int t = lane; t < nt; t += kWave) {
+        for (int t = 0; t < nt[k]; ++t) {
             TileDesc d;
             d.pos0 = pos0;
             d.key_off = ko;
@@ -101,80 +106,115 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
             d.t0 = t * T;
             d.n = nb - t * T < T ? nb - t * T : T;
             d.L = L;
-            J->tiles[D][slot + t] = d;
+            J->tiles[D][base + t] = d;
         }
-        if (nt >= 2 && !tiles_only) {
-            const int np = nt / 2;                   // phase 0 pairs (0,1), (2,3), ...
-            int s2 = 0;
-            if (lane == 0) s2 = atomicAdd(&J->mcount[0], np);
-            s2 = __shfl(s2, 0, kWave);
-            if ((int64_t)s2 + np > J->merge_cap) {
-                if (lane == 0) set_status(J, ST_OVERFLOW);
-                continue;
+        if (nt[k] < 2 || tiles_only) continue;
+        const int np = nt[k] / 2;                    // phase 0 pairs (0,1), (2,3), ...
+        const int64_t ib = blk_item_base + islot[k];
+        if (ib + np > J->merge_cap) {
+            set_status(J, ST_OVERFLOW);
+            continue;
+        }
+        for (int q = 0; q < np; ++q) {
+            MergeItem m;
+            m.pos0 = pos0;
+            m.key_off = ko;
+            m.pair_base = 0;
+            m.n_b = nb;
+            m.L = L;
+            m.T = T;
+            m.a = 2 * q;
+            m.p = nt[k];
+            m.s = 0;
+            J->mlist[0][ib + q] = m;
+        }
+    }
+}
+
+// W = ceil(L/8) big-endian uint64 lanes of the L bytes at p; bytes past L are
+// zero.  Aligned dword loads when the covering dwords lie inside [lo, hi);
+// single bytes otherwise.
+__device__ __forceinline__ void pack_word(const uint8_t* lo, const uint8_t* hi, const uint8_t* p,
+                                          int L, uint64_t* __restrict__ out, int64_t stride) {
+    const int W = lanes_for_len(L);
+    const uintptr_t addr = (uintptr_t)p;
+    const uintptr_t a4 = addr & ~(uintptr_t)3;
+    const int sh = (int)(addr & 3);
+    const int nd = (sh + L + 3) >> 2;                // dwords covering the word
+    if (a4 >= (uintptr_t)lo && a4 + 4 * (uintptr_t)nd <= (uintptr_t)hi) {
+        const uint32_t* q = (const uint32_t*)a4;
+        uint32_t prev = q[0];
+        uint64_t acc = 0;
+        const int dk = (L + 3) >> 2;                 // key dwords
+        for (int i = 0; i < dk; ++i) {
+            const uint32_t next = i + 1 < nd ? q[i + 1] : 0u;
+            const uint32_t raw = __builtin_amdgcn_alignbyte(next, prev, sh);   // bytes 4i..4i+3
+            prev = next;
+            uint32_t be = __builtin_bswap32(raw);
+            const int valid = L - 4 * i;
+            if (valid < 4) be &= 0xFFFFFFFFu << (8 * (4 - valid));
+            if ((i & 1) == 0) {
+                acc = (uint64_t)be << 32;
+            } else {
+                acc |= be;
+                out[(int64_t)(i >> 1) * stride] = acc;
             }
-            for (int k = lane; k < np; k += kWave) {
-                MergeItem m;
-                m.pos0 = pos0;
-                m.key_off = ko;
-                m.n_b = nb;
-                m.L = L;
-                m.T = T;
-                m.a = 2 * k;
-                m.p = nt;
-                m.pad = 0;
-                J->mlist[0][s2 + k] = m;
-            }
+        }
+        if (dk & 1) out[(int64_t)(dk >> 1) * stride] = acc;
+    } else {
+        for (int w = 0; w < W; ++w) {
+            uint64_t v = 0;
+            const int k1 = L - 8 * w < 8 ? L - 8 * w : 8;
+            for (int k = 0; k < k1; ++k) v |= (uint64_t)p[8 * w + k] << (56 - 8 * k);
+            out[(int64_t)w * stride] = v;
         }
     }
 }
 
 __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ J) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= J->total) return;
-    const int R = J->R;
-    const int r = upper_index(J->req_start, R, q);
-    int64_t a, b;
-    req_bounds2(J, r, a, b);
-    if (q < a || q >= b) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * kTileWavesPerBlock + wv;
+    int r;
+    int64_t a, b, gs, ge;
+    if (!chunk_range(J, c, r, a, b, gs, ge)) return;
     const int ml1 = J->ml1;
     const int32_t* cnt = J->counts + (int64_t)r * ml1;
     const int32_t* st = J->starts + (int64_t)r * (ml1 + 1);
-    const int64_t local = q - a;
-    if (local >= st[ml1]) return;                    // malformed words were left out
-    const int32_t idx = J->order[q];
-    if (idx < 0 || idx >= b - a) {
-        set_status(J, ST_OVERFLOW);
-        return;
-    }
-    const int64_t g = a + idx;
-    const int64_t o0 = J->offsets[g], o1 = J->offsets[g + 1];
-    const int64_t len = o1 - o0;
-    if (o0 < 0 || len < 0 || len > J->max_len || o1 > J->n_bytes) {
-        set_status(J, ST_BAD_OFFSETS);
-        return;
-    }
-    const int L = (int)len;
-    const int64_t j = local - st[L];
-    const int nb = cnt[L];
-    if (j < 0 || j >= nb) {
-        set_status(J, ST_BAD_REQ);
-        return;
-    }
-    const int64_t ko = J->key_off[(int64_t)r * ml1 + L];
-    const int W = lanes_for_len(L);
+    const int64_t* ko_r = J->key_off + (int64_t)r * ml1;
+    const int64_t nvalid = st[ml1];                  // malformed words were left out
     const int wmax = lanes_for_len(J->max_len);
-    if (ko < (int64_t)wmax * a || ko + (int64_t)W * nb > (int64_t)wmax * b) {
-        set_status(J, ST_BAD_REQ);
-        return;
+    const int64_t first = J->offsets[0];             // nothing below it is read
+    const uint8_t* blo = J->bytes + (first > 0 ? first : 0);
+    const uint8_t* bhi = J->bytes + J->n_bytes;
+    for (int i = 0; i < kChunkRounds; ++i) {
+        const int64_t q = gs + (int64_t)i * kWave + lane;
+        if (q >= ge) break;
+        const int64_t local = q - a;
+        if (local >= nvalid) continue;
+        const int32_t idx = J->order[q];
+        if (idx < 0 || idx >= b - a) {
+            set_status(J, ST_OVERFLOW);
+            continue;
+        }
+        const int64_t g = a + idx;
+        const int64_t o0 = J->offsets[g], o1 = J->offsets[g + 1];
+        const int64_t len = o1 - o0;
+        if (o0 < 0 || len < 0 || len > J->max_len || o1 > J->n_bytes) {
+            set_status(J, ST_BAD_OFFSETS);
+            continue;
+        }
+        const int L = (int)len;
+        const int64_t j = local - st[L];
+        const int nb = cnt[L];
+        const int64_t ko = ko_r[L];
+        if (j < 0 || j >= nb || ko < (int64_t)wmax * a ||
+            ko + (int64_t)lanes_for_len(L) * nb > (int64_t)wmax * b) {
+            set_status(J, ST_BAD_REQ);
+            continue;
+        }
+        if (L > 0) pack_word(blo, bhi, J->bytes + o0, L, J->keys + ko + j, nb);
+        J->perm[q] = idx;
     }
-    const uint8_t* p = J->bytes + o0;
-    for (int w = 0; w < W; ++w) {
-        uint64_t v = 0;
-        const int k1 = L - 8 * w < 8 ? L - 8 * w : 8;
-        for (int k = 0; k < k1; ++k) v |= (uint64_t)p[8 * w + k] << (56 - 8 * k);
-        J->keys[ko + (int64_t)w * nb + j] = v;
-    }
-    J->perm[q] = idx;
 }
 
 // record x > record y, records as SoA dwords in LDS (dword d at lds[d*tot + i])
@@ -186,9 +226,12 @@ __device__ __forceinline__ bool lds_gt(const uint32_t* lds, int tot, int D, int 
     return false;
 }
 
-// Merge-split of tiles m.a and m.a+1 of one sub-array, in place.
+// Merge-split of tiles m.a and m.a+1 of one sub-array, in place.  Both tiles
+// are loaded into LDS; each thread merges a contiguous run of outputs found
+// by a merge-path search; outputs are staged in LDS and written back
+// coalesced when 2*D*(words) dwords fit in lds_dwords, else written directly.
 __device__ void merge_pair(const Job* __restrict__ J, const MergeItem& m, bool last_phase,
-                           uint32_t* lds, int* sflag) {
+                           uint32_t* lds, int lds_dwords, int* sflag) {
     const int D = dwords_for_len(m.L), Dk = D - 1, W = lanes_for_len(m.L);
     const int64_t lo = (int64_t)m.a * m.T;
     const int na = m.T;
@@ -212,8 +255,7 @@ __device__ void merge_pair(const Job* __restrict__ J, const MergeItem& m, bool l
         *sflag = in_order;
     }
     __syncthreads();
-    const bool skip = *sflag != 0;
-    if (skip) return;                                // uniform
+    if (*sflag != 0) return;                         // uniform
 
     for (int i = tid; i < tot; i += NT) {
         const int64_t j = lo + i;
@@ -226,6 +268,8 @@ __device__ void merge_pair(const Job* __restrict__ J, const MergeItem& m, bool l
     }
     __syncthreads();
 
+    const bool staged = 2 * D * tot <= lds_dwords;
+    uint32_t* outb = lds + D * tot;
     const int E = (tot + NT - 1) / NT;
     const int k0 = tid * E;
     if (k0 < tot) {
@@ -242,15 +286,33 @@ __device__ void merge_pair(const Job* __restrict__ J, const MergeItem& m, bool l
         for (int k = k0; k < k1; ++k) {
             const bool take_a = ib >= nb || (ia < na && lds_gt(lds, tot, D, na + ib, ia));
             const int src = take_a ? ia++ : na + ib++;
+            if (staged) {
+                for (int d = 0; d < D; ++d) outb[d * tot + k] = lds[d * tot + src];
+            } else {
+                const int64_t jo = lo + k;
+                if (!last_phase) {
+                    for (int w = 0; w < W; ++w) {
+                        const uint64_t hi = lds[(2 * w) * tot + src];
+                        const uint64_t lw = (2 * w + 1 < Dk) ? lds[(2 * w + 1) * tot + src] : 0u;
+                        keys[w * nbk + jo] = (hi << 32) | lw;
+                    }
+                }
+                perm[jo] = (int32_t)lds[Dk * tot + src];
+            }
+        }
+    }
+    if (staged) {
+        __syncthreads();
+        for (int k = tid; k < tot; k += NT) {
             const int64_t jo = lo + k;
             if (!last_phase) {
                 for (int w = 0; w < W; ++w) {
-                    const uint64_t hi = lds[(2 * w) * tot + src];
-                    const uint64_t lw = (2 * w + 1 < Dk) ? lds[(2 * w + 1) * tot + src] : 0u;
+                    const uint64_t hi = outb[(2 * w) * tot + k];
+                    const uint64_t lw = (2 * w + 1 < Dk) ? outb[(2 * w + 1) * tot + k] : 0u;
                     keys[w * nbk + jo] = (hi << 32) | lw;
                 }
             }
-            perm[jo] = (int32_t)lds[Dk * tot + src];
+            perm[jo] = (int32_t)outb[Dk * tot + k];
         }
     }
 }
@@ -261,7 +323,8 @@ __device__ __forceinline__ void push_item(const Job* J, int s1, const MergeItem&
     else set_status(J, ST_OVERFLOW);
 }
 
-__global__ __launch_bounds__(1024) void k_merge_phase(const Job* __restrict__ J, int s) {
+__global__ __launch_bounds__(1024) void k_merge_phase(const Job* __restrict__ J, int s,
+                                                      int lds_dwords) {
     extern __shared__ uint32_t lds[];
     __shared__ int sflag;
     if (s >= J->phase_cap) return;
@@ -270,17 +333,19 @@ __global__ __launch_bounds__(1024) void k_merge_phase(const Job* __restrict__ J,
     const MergeItem* list = J->mlist[s & 1];
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         const MergeItem m = list[it];
-        merge_pair(J, m, s == m.p - 1, lds, &sflag);
+        merge_pair(J, m, s == m.p - 1, lds, lds_dwords, &sflag);
         if (threadIdx.x == 0 && s + 1 < m.p) {
             // successors: pair (a+1, a+2); after an odd phase also (0, 1)
             if (m.a + 2 < m.p) {
                 MergeItem n = m;
                 n.a = m.a + 1;
+                n.s = s + 1;
                 push_item(J, s + 1, n);
             }
             if ((s & 1) && m.a == 1) {
                 MergeItem n = m;
                 n.a = 0;
+                n.s = s + 1;
                 push_item(J, s + 1, n);
             }
         }
@@ -290,12 +355,12 @@ __global__ __launch_bounds__(1024) void k_merge_phase(const Job* __restrict__ J,
 
 // plain form: one launch per (sub-array, phase); block x takes pair a = (s&1) + 2x
 __global__ __launch_bounds__(1024) void k_merge_bucket(const Job* __restrict__ J, MergeItem m,
-                                                       int s) {
+                                                       int s, int lds_dwords) {
     extern __shared__ uint32_t lds[];
     __shared__ int sflag;
     m.a = (s & 1) + 2 * (int)blockIdx.x;
     if (m.a + 1 >= m.p) return;
-    merge_pair(J, m, s == m.p - 1, lds, &sflag);
+    merge_pair(J, m, s == m.p - 1, lds, lds_dwords, &sflag);
 }
 
 static inline unsigned grid_for2(int64_t items, int per_block, int64_t cap) {
@@ -305,27 +370,48 @@ static inline unsigned grid_for2(int64_t items, int per_block, int64_t cap) {
     return (unsigned)g;
 }
 
+int merge_lds_budget() {
+    static int budget = -1;
+    if (budget < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess || v <= 0)
+            v = 64 * 1024;
+        v -= 1024;                                   // room for the static __shared__ words
+        if (v > 160 * 1024) v = 160 * 1024;
+        budget = v;
+        (void)hipFuncSetAttribute((const void*)k_merge_phase,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, budget);
+        (void)hipFuncSetAttribute((const void*)k_merge_bucket,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, budget);
+    }
+    return budget;
+}
+
 hipError_t launch_pack(const Job* J, const Bounds& b, hipStream_t s) {
-    k_pack<<<grid_for2(b.total, 256, 0x7fffffff), 256, 0, s>>>(J);
+    k_pack<<<grid_for2(b.chunk_cap, kTileWavesPerBlock, 0x7fffffff), 256, 0, s>>>(J);
     return hipGetLastError();
 }
 
 hipError_t launch_merge_phase(const Job* J, const Bounds& b, int phase, hipStream_t s) {
-    const int64_t merge_cap = b.total / kMinTile + (int64_t)b.R * b.ml1;
-    k_merge_phase<<<grid_for2(merge_cap / 2 + 1, 1, 4096), b.merge_threads, b.merge_lds, s>>>(
-        J, phase);
+    const int64_t merge_cap = (b.total / kMinTile + (int64_t)b.R * b.ml1) / 2 + 1;
+    k_merge_phase<<<grid_for2(merge_cap, 1, 4096), b.merge_threads, b.merge_lds, s>>>(
+        J, phase, b.merge_lds / 4);
     return hipGetLastError();
 }
 
 hipError_t launch_merge_one_bucket(const Job* J, const MergeItem& item0, int npairs, int phase,
                                    int merge_threads, int lds, hipStream_t s) {
     if (npairs <= 0) return hipSuccess;
-    k_merge_bucket<<<npairs, merge_threads, lds, s>>>(J, item0, phase);
+    k_merge_bucket<<<npairs, merge_threads, lds, s>>>(J, item0, phase, lds / 4);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s) {
-    k_sort_init<<<1, 256, 0, s>>>(J);
+    hipError_t e = launch_chunk_plan(J, false, s);       // k_pack's chunk map
+    if (e != hipSuccess) return e;
+    k_sort_init<<<grid_for2((int64_t)b.phase_bound + kNumD + 1, 256, 1024), 256, 0, s>>>(J);
     k_tile_plan<<<grid_for2(b.R, kTileWavesPerBlock, 0x7fffffff), 256, 0, s>>>(J);
     return launch_pack(J, b, s);
 }

@@ -149,6 +149,23 @@ def test_edge_cases(bs, ws, name):
     assert np.array_equal(got_small_tiles, expect), name
 
 
+def test_sort_buckets_on_a_fresh_workspace(bs, ws):
+    """sort_buckets must not depend on what bucketize left in its workspace:
+    bucketize with one workspace, sort with another full of junk (status word
+    cleared)."""
+    w = wordgen.single(2)
+    b, o = bs.to_device(w.bytes, w.offsets)
+    counts, starts, order = bs.bucketize(b, o, 20, ws=ws)
+    bs.check_device_status(ws)
+    junk = bs.Workspace(bs.workspace_bytes(w.n, 20, 1))
+    junk.tensor.fill_(0x5A)
+    junk.tensor[:512].zero_()
+    torch.cuda.synchronize()
+    perm = bs.sort_buckets(b, o, counts, starts, order, 20, ws=junk)
+    bs.check_device_status(junk)
+    assert np.array_equal(perm.cpu().numpy(), oracle.definition_sort(w.bytes, w.offsets))
+
+
 def test_empty_list(bs, ws):
     w = wordgen.Words.from_list([])
     b, o = bs.to_device(w.bytes, w.offsets)
@@ -304,3 +321,18 @@ def test_workspace_too_small(bs):
     bk = _lib.Buckets(o.data_ptr(), o.data_ptr(), o.data_ptr())
     rc = _lib.load().bsort_bucketize(ctypes.byref(wd), ctypes.byref(bk), tiny.ptr, 256, None)
     assert rc == 4
+
+
+def test_staged_batch_equals_unstaged(bs, ws, batch_small):
+    """The stage-timed entry point records events between stages and gives
+    the same bits."""
+    sub = wordgen.Batch.concat([batch_small.request(r) for r in range(100)])
+    b, o = bs.to_device(sub.bytes, sub.offsets)
+    rs = torch.from_numpy(sub.req_start).cuda()
+    timer = bs.StageTimer(12)
+    perm = bs.sort_batch_staged(b, o, rs, sub.req_start, 12, timer, ws=ws)
+    ms = timer.ms()
+    bs.check_device_status(ws)
+    assert list(ms) == ["bucketize", "pack", "oets_d2", "oets_d3", "oets_d4", "merge_split"]
+    assert all(v >= 0 for v in ms.values())
+    assert np.array_equal(perm.cpu().numpy(), gpu_batch(bs, ws, sub, 12))

@@ -332,16 +332,17 @@ def batch(R: int = BATCH_R, first: int = 0, count: Optional[int] = None,
     """Workload 4: R independent requests, sizes log-uniform in [16, 65,536].
 
     ``first``/``count`` select a contiguous sub-range of the same R requests
-    (the same words as in the full workload)."""
+    (the same words as in the full workload).  ``workers`` > 1 generates in
+    that many worker processes (same result)."""
     sizes = batch_sizes(R, seed)
     if count is None:
         count = R - first
     ids = list(range(first, first + count))
     if workers is None:
-        workers = min(8, os.cpu_count() or 1) if count >= 512 else 1
+        workers = 1
     if workers > 1:
-        # fresh interpreters ("spawn"), so this is safe in a process that has
-        # already opened a GPU
+        # worker processes: only start them from a process that has not yet
+        # opened a GPU (a profiler's preload library may open it before main)
         ctx = multiprocessing.get_context("spawn")
         with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
             reqs = list(ex.map(batch_request, ids, [int(sizes[r]) for r in ids],
