@@ -36,50 +36,84 @@ def kmax_for(D):
     return 64 if D <= 2 else 32 if D <= 4 else 16 if D <= 8 else 8 if D <= 16 else 4
 
 
-def tile_for(D, want):
-    return min(want, 64 * kmax_for(D))
+LDS_BYTES = 144 * 1024
 
 
-def workload_structure(offsets, req_start, max_len, tile_keys):
-    """Host-side census of the work the method does on this input: per record
-    width D the odd-even transposition tiles and their compare-exchanges, and
-    the merge-split pairs and bytes.  Computed from word lengths only."""
+def lds_caps_for(D):
+    """Capacities of the in-LDS size classes for record width D (empty: none)."""
+    if not 2 <= D <= 5:
+        return []
+    top = 16384 if D <= 2 else 12288 if D == 3 else 9216 if D == 4 else 7168
+    caps = [1024 << c for c in range(4)] + [top]
+    return [c for c in caps if D * 4 * c <= LDS_BYTES]
+
+
+def lds_tile(tuned, cap):
+    """Tile size inside an in-LDS sub-array of class capacity cap."""
+    t = tuned
+    while t < cap // 32 and t < 512:
+        t <<= 1
+    return t
+
+
+def tile_ce(n, T):
+    """Compare-exchanges of odd-even transposition sorts of n words cut into
+    tiles of T: n_t(n_t-1)/2 per tile."""
+    full = n // T
+    rest = n - full * T
+    return full * (T * (T - 1) // 2) + rest * (rest - 1) // 2
+
+
+def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
+    """Host-side census of the work the method does on this input, routed as
+    the library routes it: per record width D, the compare-exchanges of
+    single-tile sub-arrays ('tiles_dD'), of tiles inside in-LDS sub-arrays
+    and the LDS bytes their merge-split phases move ('lds_dD'), and the
+    phases and bytes of the merge-split through HBM ('merge_split').
+    Computed from word lengths only."""
     lens = np.diff(offsets)
     R = len(req_start) - 1
     rid = np.repeat(np.arange(R), np.diff(req_start))
     ml1 = max_len + 1
     counts = np.bincount(rid * ml1 + lens, minlength=R * ml1).reshape(R, ml1)
     out = {}
-    merge_pairs = 0
     merge_bytes = 0
     phases_max = 0
     for L in range(1, ml1):
         D = (L + 3) // 4 + 1
         W = (L + 7) // 8
-        T = tile_for(D, tile_keys)
+        T = min(tile_keys, 64 * kmax_for(D), 1024)
+        Th = min(hbm_tile_keys, 64 * kmax_for(D))
+        caps = lds_caps_for(D)
+        cap = max(caps) if caps else 0
         n = counts[:, L].astype(np.int64)
         n = n[n >= 2]
-        if len(n) == 0:
-            continue
-        full = n // T
-        rest = n - full * T
-        ce = full * (T * (T - 1) // 2) + rest * (rest - 1) // 2
-        ntiles = full + (rest > 0)
-        d = out.setdefault(D, {"tiles": 0, "ce": 0, "words": 0})
-        d["tiles"] += int(ntiles.sum())
-        d["ce"] += int(ce.sum())
-        d["words"] += int(n.sum())
-        for p, nb in zip(ntiles, n):
-            if p < 2:
+        single = n[n <= T]
+        hbm = n[(n > max(T, cap))]
+        t = out.setdefault(f"tiles_d{D}", {"ce": 0, "words": 0, "D": D})
+        t["ce"] += int(tile_ce(single, T).sum()) + int(tile_ce(hbm, Th).sum())
+        t["words"] += int(single.sum()) + int(hbm.sum())
+        lo = T
+        for c in caps:
+            lds = n[(n > lo) & (n <= c)]
+            lo = max(lo, c)
+            if not len(lds):
                 continue
-            phases_max = max(phases_max, int(p))
-            rec = 8 * W + 4
-            for s in range(p):
-                for a in range(s & 1, p - 1, 2):
-                    tot = T + min(T, int(nb) - (a + 1) * T)
-                    merge_pairs += 1
-                    merge_bytes += 2 * tot * rec
-    return out, merge_pairs, merge_bytes, phases_max
+            Tc = lds_tile(T, c)
+            l = out.setdefault(f"lds_d{D}", {"ce": 0, "words": 0, "D": D, "lds_bytes": 0})
+            l["ce"] += int(tile_ce(lds, Tc).sum())
+            l["words"] += int(lds.sum())
+            p = (lds + Tc - 1) // Tc
+            # each phase reads and writes the paired part of the sub-array in LDS
+            l["lds_bytes"] += int((2 * 4 * D * lds * p).sum())
+        for nb in hbm:
+            p = (int(nb) + Th - 1) // Th
+            phases_max = max(phases_max, p)
+            for s_ in range(p):
+                for a in range(s_ & 1, p - 1, 2):
+                    tot = Th + min(Th, int(nb) - (a + 1) * Th)
+                    merge_bytes += 2 * tot * (8 * W + 4)
+    return out, merge_bytes, phases_max
 
 
 def cpu_info():
@@ -213,28 +247,29 @@ def main():
         del pws, pperm
 
     # ---- roofline of the dominant kernel
-    struct, merge_pairs, merge_bytes, phases_max = workload_structure(
-        batch.offsets, batch.req_start, max_len, tile or 1024)
-    oets = {k: v for k, v in stage_ms.items() if k.startswith("oets_d")}
+    struct, merge_bytes, phases_max = workload_structure(
+        batch.offsets, batch.req_start, max_len, tile or 256, 2048)
     dom = max(stage_ms, key=stage_ms.get)
-    roof = None
-    if dom.startswith("oets_d"):
-        D = int(dom[len("oets_d"):])
-        ce = struct[D]["ce"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": None, "traffic": None}
+    if dom in struct:
+        D = struct[dom]["D"]
+        ce = struct[dom]["ce"]
         ops = 3 * D * ce                       # D dword compares + 2D dword selects per CE
         achieved = ops / (stage_ms[dom] / 1e3) / 1e12
-        roof = {"bound": "alu", "kernel": f"k_oets_tiles<{D}>", "achieved": achieved,
+        kern = (f"k_bucket_lds<{D},*>" if dom.startswith("lds") else f"k_oets_tiles<{D}>")
+        roof = {"bound": "alu", "kernel": kern, "achieved": achieved,
                 "peak": PEAK_INT32_TOPS, "unit": "TOP/s", "frac": achieved / PEAK_INT32_TOPS,
-                "traffic": None, "ce_per_launch": ce,
-                "ce_per_s": ce / (stage_ms[dom] / 1e3), "ops_per_ce": 3 * D}
-    elif dom == "merge_split":
+                "traffic": None, "ce_per_launch": ce, "ce_per_s": ce / (stage_ms[dom] / 1e3),
+                "ops_per_ce": 3 * D}
+        if "lds_bytes" in struct[dom]:
+            roof["lds_merge_bytes"] = struct[dom]["lds_bytes"]
+            roof["lds_merge_tb_s"] = struct[dom]["lds_bytes"] / (stage_ms[dom] / 1e3) / 1e12
+    elif dom == "merge_split" and merge_bytes:
         achieved = merge_bytes / (stage_ms[dom] / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": "k_merge_phase", "achieved": achieved,
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                 "traffic": None, "bytes_per_step": merge_bytes}
-    else:
-        roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": None, "traffic": None}
 
     # ---- CPU baseline: the oracle (paper's procedure) on a strided sample
     cpu = None
@@ -266,13 +301,14 @@ def main():
                                f"{total} words, lengths 1-12, Zipf 1.1 over an 800-word "
                                "vocabulary per list, 5% capitalised",
                    "global_batch": batch.R, "words": total, "max_len": max_len,
-                   "tile_keys": tile or 1024, "merge_threads": mthreads or 256,
+                   "tile_keys": tile or 256, "merge_threads": mthreads or 256,
                    "tuning_source": tuned_from, "parallelism": "single GPU"},
         "graph_plan": graph,
         "per_bucket_launch": plain,
         "batched_over_per_bucket": (value / plain["value"]) if plain else None,
         "stage_ms": stage_ms,
         "merge_phases_max": phases_max,
+        "work": struct,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -84,10 +84,15 @@ typedef struct {
 
 /* Launch tuning; NULL or zero fields mean the library default. */
 typedef struct {
-    int32_t tile_keys;       /* words per odd-even transposition tile: a power of
-                                two in [128, 4096]; clamped per key width */
-    int32_t merge_threads;   /* threads per merge-split workgroup: 64..1024, multiple of 64 */
+    int32_t tile_keys;       /* words per odd-even transposition tile for sub-arrays sorted
+                                in one tile or in LDS: a power of two in [128, 4096],
+                                clamped to 1024 and per key width */
+    int32_t merge_threads;   /* threads per HBM merge-split workgroup: 64..1024, multiple
+                                of 64 */
     int32_t flags;           /* BSORT_FLAG_* */
+    int32_t hbm_tile_keys;   /* tile size for sub-arrays too large for LDS, merged
+                                through HBM: a power of two in [128, 4096], clamped per
+                                key width and LDS size */
 } bsort_tuning;
 
 /* The plain form: one kernel launch per (request, length) sub-array and per
@@ -146,9 +151,10 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
 
 /*
  * Stage timing.  A batch sort runs these stages in order: "bucketize",
- * "pack" (tile planning and key packing), one "oets_d<D>" tile-sort launch
+ * "pack" (tile planning and key packing), one "tiles_d<D>" tile-sort launch
  * per record width D = 2 .. ceil(max_len/4)+1 (D = ceil(L/4)+1 for words of
- * L bytes), and "merge_split".  bsort_stage_count(max_len) is their number
+ * L bytes), one "lds_d<D>" launch group per D = 2 .. min(5, ceil(max_len/4)+1)
+ * for sub-arrays sorted whole in LDS, and "merge_split" (phases through HBM).  bsort_stage_count(max_len) is their number
  * and bsort_stage_name(max_len, i) the name of stage i (NULL if out of
  * range).  bsort_sort_batch_staged is bsort_sort_batch that also records the
  * caller's HIP events (hipEvent_t passed as void*) on the stream: events[0]

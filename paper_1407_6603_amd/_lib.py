@@ -42,7 +42,7 @@ class Buckets(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_keys", ctypes.c_int32), ("merge_threads", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("hbm_tile_keys", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):

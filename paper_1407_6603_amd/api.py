@@ -49,8 +49,9 @@ def _check_words(bytes_t: torch.Tensor, offsets_t: torch.Tensor):
         raise ValueError("offsets must be 1-D with n_words+1 entries")
 
 
-def tuning(tile_keys: int = 0, merge_threads: int = 0, flags: int = 0) -> Tuning:
-    return Tuning(tile_keys, merge_threads, flags)
+def tuning(tile_keys: int = 0, merge_threads: int = 0, flags: int = 0,
+           hbm_tile_keys: int = 0) -> Tuning:
+    return Tuning(tile_keys, merge_threads, flags, hbm_tile_keys)
 
 
 def workspace_bytes(total_words: int, max_len: int, n_requests: int = 1) -> int:

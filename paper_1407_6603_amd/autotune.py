@@ -20,8 +20,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tune_cache.json")
-DEFAULT = (1024, 256)
-TILES = (128, 256, 512, 1024, 2048, 4096)
+DEFAULT = (256, 256)
+TILES = (128, 256, 512, 1024)
 MERGE_THREADS = (64, 128, 256, 512, 1024)
 
 

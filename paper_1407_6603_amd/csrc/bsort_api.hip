@@ -27,7 +27,8 @@ bsort_status fail(bsort_status st, const std::string& msg) {
             return fail(BSORT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int kDefaultTile = 1024;
+constexpr int kDefaultTile = 256;        // single tiles and in-LDS sub-arrays
+constexpr int kDefaultHbmTile = 2048;    // sub-arrays merged through HBM
 constexpr int kDefaultMergeThreads = 256;
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -36,8 +37,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // size a caller asks for and the layout a call uses always agree.
 struct Layout {
     size_t status, job, chunk_begin, chunk_hist, key_off, keys, tiles[kNumD], tile_count,
-        mlist[2], mcount, counts, starts, order, jobs;
-    int64_t chunk_cap, tile_cap, merge_cap;
+        mlist[2], mcount, counts, starts, order, jobs, lbuckets, lb_count;
+    int64_t chunk_cap, tile_cap, merge_cap, lb_cap;
     int32_t phase_cap, ml1, dmax, wmax;
     size_t bytes;
 };
@@ -68,6 +69,9 @@ bool make_layout(int64_t total, int32_t R, int32_t max_len, Layout& L) {
     for (int D = 2; D <= L.dmax && D <= kMaxD; ++D)
         L.tiles[D] = take(sizeof(TileDesc) * (size_t)L.tile_cap);
     L.tile_count = take(sizeof(int32_t) * kNumD);
+    L.lb_cap = 4 * (int64_t)R + 1;                    // a width class covers 4 lengths per list
+    L.lbuckets = take(sizeof(LBucket) * (size_t)L.lb_cap * (kLdsMaxD + 1) * kLdsClasses);
+    L.lb_count = take(sizeof(int32_t) * kNumD * kLdsClasses);
     L.mlist[0] = take(sizeof(MergeItem) * (size_t)L.merge_cap);
     L.mlist[1] = take(sizeof(MergeItem) * (size_t)L.merge_cap);
     L.mcount = take(sizeof(int32_t) * ((size_t)L.phase_cap + 1));
@@ -85,6 +89,9 @@ bsort_status check_tuning(const bsort_tuning* t) {
     if (!t) return BSORT_OK;
     if (t->tile_keys != 0 && (!pow2(t->tile_keys) || t->tile_keys < kMinTile || t->tile_keys > 4096))
         return fail(BSORT_E_INVALID, "tile_keys must be 0 or a power of two in [128, 4096]");
+    if (t->hbm_tile_keys != 0 &&
+        (!pow2(t->hbm_tile_keys) || t->hbm_tile_keys < kMinTile || t->hbm_tile_keys > 4096))
+        return fail(BSORT_E_INVALID, "hbm_tile_keys must be 0 or a power of two in [128, 4096]");
     if (t->merge_threads != 0 &&
         (t->merge_threads < 64 || t->merge_threads > 1024 || t->merge_threads % 64))
         return fail(BSORT_E_INVALID, "merge_threads must be 0 or a multiple of 64 in [64, 1024]");
@@ -105,22 +112,31 @@ Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
     b.dmax = L.dmax;
     b.flags = t ? t->flags : 0;
     const int want = (t && t->tile_keys) ? t->tile_keys : kDefaultTile;
+    const int want_hbm = (t && t->hbm_tile_keys) ? t->hbm_tile_keys : kDefaultHbmTile;
     const int budget = merge_lds_budget();
-    int tmin = 1 << 30, need = 0;
+    int need = 0;
+    int64_t pb = 0;
     for (int D = 2; D <= kMaxD; ++D) {
-        int T = std::min(want, kWave * kmax_for(D));
-        while (T > kMinTile && D * 2 * T * 4 > budget) T >>= 1;   // both tiles fit in LDS
+        // single tiles and tiles inside in-LDS sub-arrays
+        int T = std::min(std::min(want, kWave * kmax_for(D)), kLdsMaxTile);
         b.tile_keys[D] = T;
-        if (D <= L.dmax) {
-            tmin = std::min(tmin, T);
-            need = std::max(need, D * 2 * T * 4);
+        // sub-arrays too large for LDS: tiles merged through HBM, both tiles in LDS
+        int Th = std::min(want_hbm, kWave * kmax_for(D));
+        while (Th > kMinTile && D * 2 * Th * 4 > budget) Th >>= 1;
+        b.hbm_tile_keys[D] = Th;
+        if (D > L.dmax) continue;
+        int cap = 0;                                   // largest in-LDS sub-array for D
+        for (int c = 0; c < kLdsClasses; ++c)
+            if (lds_fits(D, c)) cap = std::max(cap, lds_cap(c, D));
+        if (n_max > std::max(cap, T)) {                // some sub-array may take the HBM path
+            need = std::max(need, D * 2 * Th * 4);
+            pb = std::max<int64_t>(pb, (n_max + Th - 1) / Th);
         }
     }
     b.merge_threads = (t && t->merge_threads) ? t->merge_threads : kDefaultMergeThreads;
     // twice the inputs when that fits: merged output staged in LDS, written coalesced
-    b.merge_lds = std::min(budget, 2 * need);
-    int64_t pb = 0;
-    if (L.dmax >= 2 && n_max >= 2) pb = (n_max + tmin - 1) / tmin;
+    b.merge_lds = std::max(1024, std::min(budget, 2 * need));
+    b.lb_cap = L.lb_cap;
     b.phase_bound = (int32_t)std::min<int64_t>(pb, L.phase_cap);
     return b;
 }
@@ -144,7 +160,11 @@ Job base_job(const Layout& L, char* ws, const Bounds& b) {
             j.tile_cap[D] = L.tile_cap;
         }
         j.tile_keys[D] = b.tile_keys[D];
+        j.hbm_tile_keys[D] = b.hbm_tile_keys[D];
     }
+    j.lbuckets = (LBucket*)(ws + L.lbuckets);
+    j.lb_count = (int32_t*)(ws + L.lb_count);
+    j.lb_cap = L.lb_cap;
     j.tile_count = (int32_t*)(ws + L.tile_count);
     j.mlist[0] = (MergeItem*)(ws + L.mlist[0]);
     j.mlist[1] = (MergeItem*)(ws + L.mlist[1]);
@@ -307,21 +327,31 @@ static Job batch_job(const Layout& L, char* ws, const Bounds& bd, const bsort_ba
     return j;
 }
 
+// stages: bucketize, pack, tiles_d2..tiles_d<dmax>, lds_d2..lds_d<min(5, dmax)>, merge_split
+static int stage_dmax(int32_t max_len) { return max_len >= 1 ? dwords_for_len(max_len) : 1; }
+static int stage_lds_max(int32_t max_len) { return std::min(stage_dmax(max_len), kLdsMaxD); }
+
 int bsort_stage_count(int32_t max_len) {
     if (max_len < 0 || max_len > BSORT_MAX_LEN) return 0;
-    const int dmax = max_len >= 1 ? dwords_for_len(max_len) : 1;
-    return 3 + (dmax >= 2 ? dmax - 1 : 0);
+    const int nd = stage_dmax(max_len) - 1;
+    const int nl = stage_lds_max(max_len) - 1;
+    return 3 + (nd > 0 ? nd : 0) + (nl > 0 ? nl : 0);
 }
 
 const char* bsort_stage_name(int32_t max_len, int i) {
-    static const char* kNames[] = {"bucketize", "pack", "oets_d2", "oets_d3", "oets_d4",
-                                   "oets_d5", "oets_d6", "oets_d7", "oets_d8", "oets_d9",
-                                   "oets_d10", "oets_d11", "oets_d12", "oets_d13", "oets_d14",
-                                   "oets_d15", "oets_d16", "oets_d17"};
+    static const char* kTiles[] = {"", "", "tiles_d2", "tiles_d3", "tiles_d4", "tiles_d5",
+                                   "tiles_d6", "tiles_d7", "tiles_d8", "tiles_d9", "tiles_d10",
+                                   "tiles_d11", "tiles_d12", "tiles_d13", "tiles_d14",
+                                   "tiles_d15", "tiles_d16", "tiles_d17"};
+    static const char* kLds[] = {"", "", "lds_d2", "lds_d3", "lds_d4", "lds_d5"};
     const int n = bsort_stage_count(max_len);
     if (i < 0 || i >= n) return nullptr;
+    if (i == 0) return "bucketize";
+    if (i == 1) return "pack";
     if (i == n - 1) return "merge_split";
-    return kNames[i];
+    const int nd = stage_dmax(max_len) - 1;
+    if (i - 2 < nd) return kTiles[i];                  // i = 2 .. nd+1 -> D = i
+    return kLds[i - nd];                               // D = 2 ..
 }
 
 static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
@@ -361,6 +391,10 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
     for (int D = 2; D <= bd.dmax && D <= kMaxD; ++D) {
         HIP_TRY(mark());
         HIP_TRY(launch_oets_tiles_one(jd, bd, D, s));
+    }
+    for (int D = 2; D <= bd.dmax && D <= kLdsMaxD; ++D) {
+        HIP_TRY(mark());
+        HIP_TRY(launch_lds_buckets(jd, bd, D, s));
     }
     HIP_TRY(mark());
     HIP_TRY(launch_merges(jd, bd, s));
@@ -569,7 +603,7 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
             start += nb;
             if (l == 0 || nb < 2) continue;
             const int D = dwords_for_len(l);
-            const int T = bd0.tile_keys[D];
+            const int T = bd0.hbm_tile_keys[D];
             const int nt = (nb + T - 1) / T;
             TileDesc td;
             td.pos0 = pos0;
@@ -590,7 +624,7 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
             m.p = nt;
             m.s = 0;
             m.pair_base = 0;
-            const int lds = bd0.merge_lds;
+            const int lds = std::min(merge_lds_budget(), 2 * D * 2 * T * 4);
             for (int ph = 0; ph < nt; ++ph) {
                 const int npairs = (nt - (ph & 1)) / 2;
                 HIP_TRY(launch_merge_one_bucket(&jobs[r], m, npairs, ph, bd0.merge_threads, lds, s));

@@ -46,6 +46,33 @@ enum : uint32_t {
     ST_STALLED = 16u,      // a bounded wait in the merge scheduler gave up (a library bug)
 };
 
+// In-LDS sub-arrays: one workgroup holds a whole sub-array of up to
+// lds_cap(c, D) words in LDS (D dwords per word, at most 144 KiB) and sorts
+// it there.  Size classes c = 0..4; the largest class is sized per width D.
+constexpr int kLdsClasses = 5;
+constexpr int kLdsMaxD = 5;
+constexpr int kLdsBytes = 144 * 1024;
+__host__ __device__ constexpr int lds_cap(int c, int D) {
+    return c < 4 ? (1024 << c) : (D <= 2 ? 16384 : D == 3 ? 12288 : D == 4 ? 9216 : 7168);
+}
+__host__ __device__ constexpr bool lds_fits(int D, int c) {
+    return D >= 2 && D <= kLdsMaxD && D * 4 * lds_cap(c, D) <= kLdsBytes;
+}
+// threads per workgroup: 1024 only where the staged merge outputs still fit
+// the 128 VGPRs a 1024-thread workgroup leaves each lane (D <= 3)
+__host__ __device__ constexpr int lds_threads(int c, int D) {
+    return c <= 1 ? 256 : (c == 2 || D >= 4) ? 512 : 1024;
+}
+constexpr int kLdsMaxTile = 1024;         // tiles inside an LDS sub-array: K <= 16
+// tile size inside an in-LDS sub-array of class capacity cap when the tiles
+// are merged: the tuned tile doubled until there are at most ~32 merge-split
+// phases (cap/32 words), capped at 512 words
+__host__ __device__ constexpr int lds_tile(int tuned, int cap) {
+    int t = tuned;
+    while (t < cap / 32 && t < 512) t <<= 1;
+    return t;
+}
+
 // queue control words (Job.qctl)
 enum { Q_HEAD = 0, Q_TAIL = 1, Q_TOTAL = 2, Q_ABORT = 3, Q_ARR = 4, Q_WORDS = 8 };
 
@@ -68,6 +95,13 @@ struct TileDesc {            // one odd-even transposition tile
     int32_t t0;              // first bucket word of this tile
     int32_t n;               // words in this tile
     int32_t L;               // word length
+};
+
+struct LBucket {             // a sub-array sorted entirely in LDS
+    int64_t pos0;
+    int64_t key_off;
+    int32_t n_b;
+    int32_t L;
 };
 
 struct MergeItem {           // merge-split of tiles a and a+1 of a bucket at phase s
@@ -107,8 +141,12 @@ struct Job {
     uint64_t* keys;              // [wmax * total]
     TileDesc* tiles[kNumD];      // per record width D
     int64_t tile_cap[kNumD];
-    int32_t tile_keys[kNumD];    // tile size per D
+    int32_t tile_keys[kNumD];    // tile size per D: single tiles and in-LDS sub-arrays
+    int32_t hbm_tile_keys[kNumD];  // tile size of sub-arrays merged through HBM
     int32_t* tile_count;         // [kNumD]
+    LBucket* lbuckets;           // [kNumD * kLdsClasses][lb_cap]
+    int32_t* lb_count;           // [kNumD * kLdsClasses]
+    int64_t lb_cap;
     // per-phase merge-split lists (phase s reads mlist[s&1], queues into the other)
     MergeItem* mlist[2];
     int64_t merge_cap;
@@ -223,6 +261,8 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
     int32_t merge_threads;
     int32_t merge_lds;       // dynamic LDS bytes per merge workgroup
     int32_t tile_keys[kNumD];
+    int32_t hbm_tile_keys[kNumD];
+    int64_t lb_cap;
     int32_t flags;
 };
 
@@ -232,6 +272,7 @@ hipError_t launch_chunk_plan(const Job* J, bool clear_status, hipStream_t s);
 hipError_t launch_sort(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
+hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_merge_phase(const Job* J, const Bounds& b, int phase, hipStream_t s);
 // plain per-bucket form pieces

@@ -144,80 +144,128 @@ __device__ __forceinline__ void phases_int(uint32_t (&r)[K][D], int nph, int lan
     }
 }
 
-template <int D, int K>
-__device__ __forceinline__ void oets_tile(const Job* __restrict__ J, const TileDesc& t,
-                                          bool write_keys, int lane) {
-    static_assert(K >= 2 && (K & 1) == 0, "K must be even");
-    constexpr int Dk = D - 1;            // key dwords
-    constexpr int W = (Dk + 1) / 2;      // uint64 lanes
-    uint32_t r[K][D];
-    uint64_t* __restrict__ keys = J->keys + t.key_off;
-    int32_t* __restrict__ perm = J->perm + t.pos0;
-    const int64_t nbk = t.n_b;
-    const int jbase = t.t0 + lane * K;
-    const int jend = t.t0 + t.n;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int j = jbase + k;
-        if (j < jend) {
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const uint64_t v = keys[w * nbk + j];
-                r[k][2 * w] = (uint32_t)(v >> 32);
-                if (2 * w + 1 < Dk) r[k][2 * w + 1] = (uint32_t)v;
-            }
-            r[k][Dk] = (uint32_t)perm[j];
-        } else {
-#pragma unroll
-            for (int d = 0; d < D; ++d) r[k][d] = 0xFFFFFFFFu;
-        }
-    }
+// ---- tile sources: where a wave's K records per lane come from and go back to
 
-    const int nph = t.n;
-    if constexpr (D == 2) {
-        bool ok = true;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (jbase + k < jend && r[k][0] >= kF64KeyLimit) ok = false;
-        if (__all(ok)) phases_f64<K>(r, nph);
-        else phases_int<D, K>(r, nph, lane);
-    } else {
-        phases_int<D, K>(r, nph, lane);
-    }
+// A tile in HBM: key lanes and index payload of bucket words [t0, t0+n).
+struct HbmTile {
+    uint64_t* keys;
+    int32_t* perm;
+    int64_t nbk;
+    int t0, n;
+    bool write_keys;
 
+    template <int D, int K>
+    __device__ __forceinline__ void load(uint32_t (&r)[K][D], int lane) const {
+        constexpr int Dk = D - 1, W = (Dk + 1) / 2;
+        const int jbase = t0 + lane * K, jend = t0 + n;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int j = jbase + k;
-        if (j < jend) {
-            perm[j] = (int32_t)r[k][Dk];
-            if (write_keys) {
+        for (int k = 0; k < K; ++k) {
+            const int j = jbase + k;
+            if (j < jend) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    const uint64_t hi = r[k][2 * w];
-                    const uint64_t lo = (2 * w + 1 < Dk) ? r[k][2 * w + 1] : 0u;
-                    keys[w * nbk + j] = (hi << 32) | lo;
+                    const uint64_t v = keys[w * nbk + j];
+                    r[k][2 * w] = (uint32_t)(v >> 32);
+                    if (2 * w + 1 < Dk) r[k][2 * w + 1] = (uint32_t)v;
+                }
+                r[k][Dk] = (uint32_t)perm[j];
+            } else {
+#pragma unroll
+                for (int d = 0; d < D; ++d) r[k][d] = 0xFFFFFFFFu;
+            }
+        }
+    }
+    template <int D, int K>
+    __device__ __forceinline__ void store(const uint32_t (&r)[K][D], int lane) const {
+        constexpr int Dk = D - 1, W = (Dk + 1) / 2;
+        const int jbase = t0 + lane * K, jend = t0 + n;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int j = jbase + k;
+            if (j < jend) {
+                perm[j] = (int32_t)r[k][Dk];
+                if (write_keys) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const uint64_t hi = r[k][2 * w];
+                        const uint64_t lo = (2 * w + 1 < Dk) ? r[k][2 * w + 1] : 0u;
+                        keys[w * nbk + j] = (hi << 32) | lo;
+                    }
                 }
             }
         }
     }
+};
+
+// A tile of records held in LDS as SoA dwords (dword d of record i at
+// lds[d*cap + i]), records [t0, t0+n).
+struct LdsTile {
+    uint32_t* lds;
+    int cap;
+    int t0, n;
+
+    template <int D, int K>
+    __device__ __forceinline__ void load(uint32_t (&r)[K][D], int lane) const {
+        const int jbase = t0 + lane * K, jend = t0 + n;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int j = jbase + k;
+#pragma unroll
+            for (int d = 0; d < D; ++d) r[k][d] = j < jend ? lds[d * cap + j] : 0xFFFFFFFFu;
+        }
+    }
+    template <int D, int K>
+    __device__ __forceinline__ void store(const uint32_t (&r)[K][D], int lane) const {
+        const int jbase = t0 + lane * K, jend = t0 + n;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int j = jbase + k;
+            if (j < jend) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) lds[d * cap + j] = r[k][d];
+            }
+        }
+    }
+};
+
+template <int D, int K, class Src>
+__device__ __forceinline__ void sort_tile(const Src& src, int n, int lane) {
+    static_assert(K >= 2 && (K & 1) == 0, "K must be even");
+    uint32_t r[K][D];
+    src.template load<D, K>(r, lane);
+    if constexpr (D == 2) {
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (lane * K + k < n && r[k][0] >= kF64KeyLimit) ok = false;
+        if (__all(ok)) phases_f64<K>(r, n);
+        else phases_int<D, K>(r, n, lane);
+    } else {
+        phases_int<D, K>(r, n, lane);
+    }
+    src.template store<D, K>(r, lane);
 }
 
-// smallest supported K >= kneed (kneed <= kmax_for(D) by construction)
-template <int D, int K>
-__device__ __forceinline__ void run_tile_k(const Job* J, const TileDesc& t, bool wk, int lane,
-                                           int kneed) {
-    if constexpr (K * 2 > kmax_for(D)) {
-        oets_tile<D, K>(J, t, wk, lane);
+// smallest supported K >= kneed, K <= KCAP (kneed <= KCAP by construction)
+template <int D, int K, int KCAP, class Src>
+__device__ __forceinline__ void sort_tile_k(const Src& src, int n, int lane, int kneed) {
+    if constexpr (K * 2 > KCAP) {
+        sort_tile<D, K>(src, n, lane);
     } else {
-        if (kneed <= K) oets_tile<D, K>(J, t, wk, lane);
-        else run_tile_k<D, K * 2>(J, t, wk, lane, kneed);
+        if (kneed <= K) sort_tile<D, K>(src, n, lane);
+        else sort_tile_k<D, K * 2, KCAP>(src, n, lane, kneed);
     }
+}
+
+template <int D, int KCAP, class Src>
+__device__ __forceinline__ void sort_tile_any(const Src& src, int n, int lane) {
+    sort_tile_k<D, 2, KCAP>(src, n, lane, (n + kWave - 1) / kWave);
 }
 
 template <int D>
 __device__ __forceinline__ void run_tile(const Job* J, const TileDesc& t, bool wk, int lane) {
-    const int kneed = (t.n + kWave - 1) / kWave;
-    run_tile_k<D, 2>(J, t, wk, lane, kneed);
+    HbmTile src{J->keys + t.key_off, J->perm + t.pos0, t.n_b, t.t0, t.n, wk};
+    sort_tile_any<D, kmax_for(D)>(src, t.n, lane);
 }
 
 template <int D>
@@ -226,12 +274,12 @@ __global__ __launch_bounds__(256) void k_oets_tiles(const Job* __restrict__ J) {
     int64_t cnt = J->tile_count[D];
     if (cnt > J->tile_cap[D]) cnt = J->tile_cap[D];
     const TileDesc* tl = J->tiles[D];
-    const int T = J->tile_keys[D];
+    const int T = J->hbm_tile_keys[D];
     const bool tiles_only = (J->flags & kFlagTilesOnly) != 0;
     for (int64_t i = (int64_t)blockIdx.x * kTileWavesPerBlock + wv; i < cnt;
          i += (int64_t)gridDim.x * kTileWavesPerBlock) {
         const TileDesc t = tl[i];
-        const bool wk = t.n_b > T && !tiles_only;   // merge-split reads the keys back
+        const bool wk = t.n_b > T && !tiles_only;   // merge-split through HBM reads keys back
         run_tile<D>(J, t, wk, lane);
     }
 }
@@ -244,6 +292,178 @@ __global__ __launch_bounds__(64) void k_oets_bucket(const Job* __restrict__ J, T
     t.t0 = (int)blockIdx.x * T;
     t.n = t.n_b - t.t0 < T ? t.n_b - t.t0 : T;
     run_tile<D>(J, t, wk != 0, lane);
+}
+
+// ---- whole sub-arrays in LDS
+//
+// One workgroup per sub-array of T < n <= CAP words: the sub-array is read
+// into LDS once; its ceil(n/T) tiles are sorted by odd-even transposition in
+// registers (one wave per tile); then the p = ceil(n/T) phases of the block
+// odd-even merge-split run in LDS.  In phase s the pairs (a, a+1), a = s mod
+// 2, s mod 2 + 2, ..., are merged; each thread produces up to CAP/NT
+// consecutive outputs of one phase (found by a merge-path search), holds them
+// in registers, and after a barrier writes them back in place.  Only the
+// final index payload is written to HBM.
+
+template <int D>
+__device__ __forceinline__ void lds_rec(const uint32_t* lds, int cap, int i, uint32_t (&x)[D]) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[d] = lds[d * cap + i];
+}
+
+// merge path in pair (lo .. lo+na+nb): number of the first i0 outputs taken
+// from the lower tile
+template <int D>
+__device__ __forceinline__ int lds_merge_path(const uint32_t* lds, int cap, int lo, int na,
+                                              int nb, int i0) {
+    int a = i0 - nb > 0 ? i0 - nb : 0;
+    int b = i0 < na ? i0 : na;
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        uint32_t x[D], y[D];
+        lds_rec<D>(lds, cap, lo + mid, x);
+        lds_rec<D>(lds, cap, lo + na + (i0 - 1 - mid), y);
+        if (rec_gt<D>(y, x)) a = mid + 1;   // lower[mid] precedes upper[i0-1-mid]
+        else b = mid;
+    }
+    return a;
+}
+
+// One output stream of a merge-split phase: consecutive output positions,
+// crossing at most one boundary between pairs of the phase.
+template <int D>
+struct MergeChain {
+    int a, lo, nb, end, ia, ib;
+    uint32_t ca[D], cb[D];
+
+    __device__ __forceinline__ void start(const uint32_t* lds, int cap, int n, int T, int U0,
+                                          int off, int pos) {
+        a = off + 2 * ((pos - U0) / (2 * T));          // pair holding position pos
+        lo = a * T;
+        nb = n - (a + 1) * T < T ? n - (a + 1) * T : T;
+        end = lo + T + nb;
+        ia = lds_merge_path<D>(lds, cap, lo, T, nb, pos - lo);
+        ib = pos - lo - ia;
+        lds_rec<D>(lds, cap, ia < T ? lo + ia : lo, ca);
+        lds_rec<D>(lds, cap, ib < nb ? lo + T + ib : lo, cb);
+    }
+
+    // output for position k (the previous output was k-1, or k is the start)
+    __device__ __forceinline__ void step(const uint32_t* lds, int cap, int n, int T, int k,
+                                         uint32_t (&o)[D]) {
+        if (k == end) {                                 // next pair of the phase starts here
+            a += 2;
+            lo = end;
+            nb = n - (a + 1) * T < T ? n - (a + 1) * T : T;
+            end = lo + T + nb;
+            ia = 0;
+            ib = 0;
+            lds_rec<D>(lds, cap, lo, ca);
+            lds_rec<D>(lds, cap, lo + T, cb);
+        }
+        const bool take_a = ib >= nb || (ia < T && !rec_gt<D>(ca, cb));
+        // selects as masks: keeps ca/cb/o in registers (no select of arrays)
+        const uint32_t m = take_a ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+        for (int d = 0; d < D; ++d) o[d] = cb[d] ^ ((ca[d] ^ cb[d]) & m);
+        ia += take_a ? 1 : 0;
+        ib += take_a ? 0 : 1;
+        const int nxt = take_a ? (ia < T ? lo + ia : lo) : (ib < nb ? lo + T + ib : lo);
+        uint32_t x[D];
+        lds_rec<D>(lds, cap, nxt, x);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ca[d] = ca[d] ^ ((x[d] ^ ca[d]) & m);
+            cb[d] = x[d] ^ ((cb[d] ^ x[d]) & m);
+        }
+    }
+};
+
+template <int D, int NT, int CAP>
+__device__ void lds_merge_phase(uint32_t* lds, int n, int T, int p, int s, int tid) {
+    constexpr int EMAX = (CAP + NT - 1) / NT;
+    constexpr int EH = (EMAX + 1) / 2;                // outputs per chain
+    const int off = s & 1;
+    if (p - 2 < off) return;                          // no pair in this phase (uniform)
+    const int a_last = p - 2 - ((p - 2 - off) & 1);   // last lower tile of the phase
+    const int U0 = off * T;
+    const int U1 = (a_last + 2) * T < n ? (a_last + 2) * T : n;
+    const int E = (n + NT - 1) / NT;                  // <= EMAX since n <= CAP
+    const int k0 = tid * E < n ? tid * E : n;
+    const int k1 = k0 + E < n ? k0 + E : n;
+    const int ps = k0 > U0 ? k0 : U0;
+    const int pe = k1 < U1 ? k1 : U1;
+    const int count = pe > ps ? pe - ps : 0;
+    // two independent chains halve the dependent LDS-load chain per thread
+    const int c0 = (count + 1) / 2, c1 = count - c0;
+    const int pm = ps + c0;
+
+    uint32_t out[2 * EH][D];
+    MergeChain<D> m0, m1;
+    if (c0 > 0) m0.start(lds, CAP, n, T, U0, off, ps);
+    if (c1 > 0) m1.start(lds, CAP, n, T, U0, off, pm);
+#pragma unroll
+    for (int j = 0; j < EH; ++j) {
+        if (j < c0) m0.step(lds, CAP, n, T, ps + j, out[j]);
+        if (j < c1) m1.step(lds, CAP, n, T, pm + j, out[EH + j]);
+    }
+    __syncthreads();                                   // every read of this phase is done
+#pragma unroll
+    for (int j = 0; j < EH; ++j) {
+        if (j < c0) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) lds[d * CAP + ps + j] = out[j][d];
+        }
+        if (j < c1) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) lds[d * CAP + pm + j] = out[EH + j][d];
+        }
+    }
+    __syncthreads();
+}
+
+template <int D, int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, int cls) {
+    __shared__ uint32_t lds[D * CAP];
+    constexpr int NW = NT / kWave;
+    constexpr int Dk = D - 1, W = (Dk + 1) / 2;
+    constexpr int KCAP = kmax_for(D) < kLdsMaxTile / kWave ? kmax_for(D) : kLdsMaxTile / kWave;
+    static_assert(D * CAP * 4 <= kLdsBytes, "sub-array does not fit the LDS budget");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int slot = D * kLdsClasses + cls;
+    int64_t cnt = J->lb_count[slot];
+    if (cnt > J->lb_cap) cnt = J->lb_cap;
+    const LBucket* list = J->lbuckets + slot * J->lb_cap;
+    const bool tiles_only = (J->flags & kFlagTilesOnly) != 0;
+    const int T = tiles_only ? J->tile_keys[D] : lds_tile(J->tile_keys[D], CAP);
+    for (int64_t bi = blockIdx.x; bi < cnt; bi += gridDim.x) {
+        const LBucket bk = list[bi];
+        const int n = bk.n_b;                          // T < n <= CAP (checked when listed)
+        const uint64_t* keys = J->keys + bk.key_off;
+        int32_t* perm = J->perm + bk.pos0;
+        for (int i = tid; i < n; i += NT) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint64_t v = keys[(int64_t)w * n + i];
+                lds[(2 * w) * CAP + i] = (uint32_t)(v >> 32);
+                if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + i] = (uint32_t)v;
+            }
+            lds[Dk * CAP + i] = (uint32_t)perm[i];
+        }
+        __syncthreads();
+        const int p = (n + T - 1) / T;
+        for (int t = wv; t < p; t += NW) {
+            const int t0 = t * T;
+            const int tn = n - t0 < T ? n - t0 : T;
+            LdsTile src{lds, CAP, t0, tn};
+            sort_tile_any<D, KCAP>(src, tn, lane);
+        }
+        __syncthreads();
+        if (!tiles_only)
+            for (int s = 0; s < p; ++s) lds_merge_phase<D, NT, CAP>(lds, n, T, p, s, tid);
+        for (int i = tid; i < n; i += NT) perm[i] = (int32_t)lds[Dk * CAP + i];
+        __syncthreads();                               // LDS reused by the next sub-array
+    }
 }
 
 template <int D>
@@ -276,6 +496,35 @@ static const BucketLauncher kBucketLaunchers[kNumD] = {
     launch_bucket_d<9>, launch_bucket_d<10>, launch_bucket_d<11>, launch_bucket_d<12>,
     launch_bucket_d<13>, launch_bucket_d<14>, launch_bucket_d<15>, launch_bucket_d<16>,
     launch_bucket_d<17>};
+
+template <int D, int C>
+static void launch_lds_class(const Job* J, int64_t lb_cap, hipStream_t s) {
+    if constexpr (lds_fits(D, C)) {
+        int64_t g = lb_cap < 1024 ? lb_cap : 1024;
+        if (g < 1) g = 1;
+        k_bucket_lds<D, lds_threads(C, D), lds_cap(C, D)><<<(unsigned)g, lds_threads(C, D), 0, s>>>(J, C);
+    }
+}
+
+template <int D>
+static void launch_lds_d(const Job* J, int64_t lb_cap, hipStream_t s) {
+    launch_lds_class<D, 0>(J, lb_cap, s);
+    launch_lds_class<D, 1>(J, lb_cap, s);
+    launch_lds_class<D, 2>(J, lb_cap, s);
+    launch_lds_class<D, 3>(J, lb_cap, s);
+    launch_lds_class<D, 4>(J, lb_cap, s);
+}
+
+hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s) {
+    switch (D) {
+        case 2: launch_lds_d<2>(J, b.lb_cap, s); break;
+        case 3: launch_lds_d<3>(J, b.lb_cap, s); break;
+        case 4: launch_lds_d<4>(J, b.lb_cap, s); break;
+        case 5: launch_lds_d<5>(J, b.lb_cap, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s) {
     if (D < 2 || D > kMaxD) return hipErrorInvalidValue;

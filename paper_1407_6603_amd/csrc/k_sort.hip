@@ -23,6 +23,7 @@ __global__ __launch_bounds__(256) void k_sort_init(const Job* __restrict__ J) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     if (i0 < kNumD) J->tile_count[i0] = 0;
+    if (i0 < kNumD * kLdsClasses) J->lb_count[i0] = 0;
     for (int64_t i = i0; i <= J->phase_cap; i += step) J->mcount[i] = 0;
 }
 
@@ -34,8 +35,11 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     __shared__ int64_t blk_tile_base[kNumD];
     __shared__ int blk_items;
     __shared__ int64_t blk_item_base;
+    __shared__ int blk_lb[kNumD * kLdsClasses];
+    __shared__ int64_t blk_lb_base[kNumD * kLdsClasses];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid < kNumD) blk_tiles[tid] = 0;
+    if (tid < kNumD * kLdsClasses) blk_lb[tid] = 0;
     if (tid == 0) blk_items = 0;
     __syncthreads();
 
@@ -49,8 +53,10 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     const int32_t* cnt = J->counts + (int64_t)(active ? r : 0) * ml1;
     const int32_t* st = J->starts + (int64_t)(active ? r : 0) * (ml1 + 1);
 
-    // per length L = lane + 64*k (k = 0, 1): tiles, tile slot, merge slot
-    int nt[2] = {0, 0}, tslot[2] = {0, 0}, islot[2] = {0, 0};
+    // per length L = lane + 64*k (k = 0, 1): route, tiles, tile slot, merge slot.
+    // route: 0 none, 1 one register tile, 2 whole sub-array in LDS (class lcls),
+    // 3 HBM tiles merged phase by phase
+    int nt[2] = {0, 0}, tslot[2] = {0, 0}, islot[2] = {0, 0}, route[2] = {0, 0}, lcls[2] = {0, 0};
     if (active) {
         int64_t run = (int64_t)wmax * a;    // uint64 offset of each sub-array's lane 0
         for (int k = 0; k < 2; ++k) {
@@ -72,27 +78,59 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
                 continue;
             }
             const int D = dwords_for_len(L);
-            const int T = J->tile_keys[D];
-            nt[k] = (nb + T - 1) / T;
-            tslot[k] = atomicAdd(&blk_tiles[D], nt[k]);
-            if (nt[k] >= 2 && !tiles_only) islot[k] = atomicAdd(&blk_items, nt[k] / 2);
+            int c = -1;
+            if (nb > J->tile_keys[D])
+                for (int q = 0; q < kLdsClasses; ++q)
+                    if (c < 0 && lds_fits(D, q) && nb <= lds_cap(q, D)) c = q;
+            if (nb <= J->tile_keys[D]) {
+                route[k] = 1;
+                nt[k] = 1;
+                tslot[k] = atomicAdd(&blk_tiles[D], 1);
+            } else if (c >= 0) {
+                route[k] = 2;
+                lcls[k] = c;
+                tslot[k] = atomicAdd(&blk_lb[D * kLdsClasses + c], 1);
+            } else {
+                route[k] = 3;
+                const int T = J->hbm_tile_keys[D];
+                nt[k] = (nb + T - 1) / T;
+                tslot[k] = atomicAdd(&blk_tiles[D], nt[k]);
+                if (nt[k] >= 2 && !tiles_only) islot[k] = atomicAdd(&blk_items, nt[k] / 2);
+            }
         }
     }
     __syncthreads();
     if (tid < kNumD && blk_tiles[tid] > 0)
         blk_tile_base[tid] = atomicAdd(&J->tile_count[tid], blk_tiles[tid]);
     if (tid == kNumD && blk_items > 0) blk_item_base = atomicAdd(&J->mcount[0], blk_items);
+    if (tid < kNumD * kLdsClasses && blk_lb[tid] > 0)
+        blk_lb_base[tid] = atomicAdd(&J->lb_count[tid], blk_lb[tid]);
     __syncthreads();
     if (!active) return;
 
     for (int k = 0; k < 2; ++k) {
-        if (nt[k] == 0) continue;
+        if (route[k] == 0) continue;
         const int L = lane + kWave * k;
         const int nb = cnt[L];
         const int D = dwords_for_len(L);
-        const int T = J->tile_keys[D];
         const int64_t pos0 = a + st[L];
         const int64_t ko = kos[wv][L];
+        if (route[k] == 2) {
+            const int sl = D * kLdsClasses + lcls[k];
+            const int64_t at = blk_lb_base[sl] + tslot[k];
+            if (at >= J->lb_cap) {
+                set_status(J, ST_OVERFLOW);
+                continue;
+            }
+            LBucket lb;
+            lb.pos0 = pos0;
+            lb.key_off = ko;
+            lb.n_b = nb;
+            lb.L = L;
+            J->lbuckets[sl * J->lb_cap + at] = lb;
+            continue;
+        }
+        const int T = route[k] == 1 ? nb : J->hbm_tile_keys[D];
         const int64_t base = blk_tile_base[D] + tslot[k];
         if (base + nt[k] > J->tile_cap[D]) {
             set_status(J, ST_OVERFLOW);
@@ -430,6 +468,10 @@ hipError_t launch_sort(const Job* J, const Bounds& b, hipStream_t s) {
     if (e != hipSuccess) return e;
     for (int D = 2; D <= b.dmax && D <= kMaxD; ++D) {
         e = launch_oets_tiles_one(J, b, D, s);
+        if (e != hipSuccess) return e;
+    }
+    for (int D = 2; D <= b.dmax && D <= kLdsMaxD; ++D) {
+        e = launch_lds_buckets(J, b, D, s);
         if (e != hipSuccess) return e;
     }
     e = launch_merges(J, b, s);

@@ -84,13 +84,24 @@ def test_tuning_does_not_change_bits(bs, ws, tile, mt):
     assert np.array_equal(got, expect)
 
 
+@pytest.mark.parametrize("tile,hbm_tile,mt", [(128, 128, 64), (256, 2048, 256), (1024, 4096, 1024),
+                                              (512, 256, 512)])
+def test_hbm_and_lds_paths_workload3(bs, ws, tile, hbm_tile, mt):
+    """250,000 words: sub-arrays up to ~50,000 words exceed LDS and take the
+    HBM merge-split path; the rest are sorted whole in LDS."""
+    w = wordgen.single(3)
+    expect = oracle.definition_sort(w.bytes, w.offsets)
+    got = gpu_sort(bs, ws, w, 24, tune=bs.tuning(tile, mt, 0, hbm_tile))
+    assert np.array_equal(got, expect)
+
+
 def test_tiles_only_sorts_each_tile(bs, ws):
     """With the merge-split switched off every tile is sorted on its own:
     tile t of a sub-array is the sorted form of its slice of the stable
     sub-array order (seams between tiles are not merged)."""
     w = wordgen.single(2)
     T = 128
-    got = gpu_sort(bs, ws, w, 20, tune=bs.tuning(T, 0, bs.FLAG_TILES_ONLY))
+    got = gpu_sort(bs, ws, w, 20, tune=bs.tuning(T, 0, bs.FLAG_TILES_ONLY, hbm_tile_keys=T))
     counts, starts, order = oracle.bucketize(w.bytes, w.offsets, 20)
     wl = w.as_list()
     for L in range(1, 21):
@@ -187,10 +198,11 @@ def test_repeat_is_deterministic(bs, ws):
 
 # ------------------------------------------------------------- 0-1 principle
 
-def zero_one_batch(seqs):
+def zero_one_batch(seqs, width=1):
+    pad = b"0" * (width - 1)
     words = []
     for s in seqs:
-        words.extend(b"1" if x else b"0" for x in s)
+        words.extend(pad + (b"1" if x else b"0") for x in s)
     req = np.zeros(len(seqs) + 1, dtype=np.int64)
     np.cumsum([len(s) for s in seqs], out=req[1:])
     w = wordgen.Words.from_list(words)
@@ -229,8 +241,49 @@ def test_zero_one_merge_seams(bs, ws, T):
         for _ in range(40):
             p = rng.random()
             seqs.append((rng.random(n) < p).astype(np.int8))
+    # past the largest in-LDS sub-array: tiles merged phase by phase through HBM
+    for n in (16385, 16384 + 3 * T + 1, 20000):
+        for _ in range(3):
+            p = rng.random()
+            seqs.append((rng.random(n) < p).astype(np.int8))
     batch = zero_one_batch(seqs)
-    got = gpu_batch(bs, ws, batch, 1, tune=bs.tuning(T, 64))
+    got = gpu_batch(bs, ws, batch, 1, tune=bs.tuning(T, 64, 0, T))
+    assert np.array_equal(got, zero_one_expect(seqs))
+
+
+def lds_caps(D):
+    """In-LDS size-class capacities for record width D (largest class per
+    width within 144 KiB of LDS)."""
+    top = {2: 16384, 3: 12288, 4: 9216, 5: 7168}[D]
+    return [c for c in (1024, 2048, 4096, 8192, top) if D * 4 * c <= 144 * 1024]
+
+
+def lds_tile(tuned, cap):
+    t = tuned
+    while t < cap // 32 and t < 512:
+        t <<= 1
+    return t
+
+
+@pytest.mark.parametrize("L", [1, 5, 9, 13])
+def test_zero_one_lds_classes(bs, ws, L):
+    """0/1 keys of width L (record widths D = 2..5) at the bounds of every
+    in-LDS size class, one class tile past each lower bound, and past the
+    largest class (merge-split through HBM): the stable partition."""
+    T = 128
+    D = (L + 3) // 4 + 1
+    rng = np.random.default_rng(1000 + L)
+    sizes, prev = [], T
+    for cap in lds_caps(D):
+        sizes += [prev + 1, prev + lds_tile(T, cap) + 1, cap - 1, cap]
+        prev = cap
+    sizes += [prev + 1, prev + 3 * T + 1]
+    seqs = []
+    for n in sizes:
+        p = rng.random()
+        seqs.append((rng.random(n) < p).astype(np.int8))
+    batch = zero_one_batch(seqs, L)
+    got = gpu_batch(bs, ws, batch, L, tune=bs.tuning(T, 64, 0, T))
     assert np.array_equal(got, zero_one_expect(seqs))
 
 
@@ -333,6 +386,7 @@ def test_staged_batch_equals_unstaged(bs, ws, batch_small):
     perm = bs.sort_batch_staged(b, o, rs, sub.req_start, 12, timer, ws=ws)
     ms = timer.ms()
     bs.check_device_status(ws)
-    assert list(ms) == ["bucketize", "pack", "oets_d2", "oets_d3", "oets_d4", "merge_split"]
+    assert list(ms) == ["bucketize", "pack", "tiles_d2", "tiles_d3", "tiles_d4",
+                        "lds_d2", "lds_d3", "lds_d4", "merge_split"]
     assert all(v >= 0 for v in ms.values())
     assert np.array_equal(perm.cpu().numpy(), gpu_batch(bs, ws, sub, 12))
