@@ -30,6 +30,47 @@ import wordgen  # noqa: E402
 
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12     # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T ops/s
 PEAK_HBM_GBS = 8000.0
+PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 128 B/clk/CU LDS bandwidth: 78.6 TB/s
+
+
+# HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counter runs in
+# profiles/batch4096_hbm_traffic.md (scaled by the plain-copy calibration
+# there), with a digest of the kernel sources they were taken on: a kernel
+# changed since then reports no traffic.
+KERNEL_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
+TRAFFIC = {
+    "k_bucket_lds<2, 1024, 8192>": {"read": 80752723, "write": 61130048,
+                                    "sources": "9009dafa700b20b8"},
+}
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    t = TRAFFIC.get(kernel)
+    if t is None or t["sources"] != sources_digest():
+        return None
+    return t["read"] + t["write"]
+
+
+def lds_threads(cap_index, D):
+    return 256 if cap_index <= 1 else 512 if (cap_index == 2 or D >= 4) else 1024
+
+
+def kernel_name(stage):
+    """The kernel behind a tile or in-LDS stage name."""
+    if stage.startswith("tiles_d"):
+        return f"k_oets_tiles<{int(stage[7:])}>"
+    D, cap = (int(x) for x in stage[5:].split("_"))
+    c = lds_caps_for(D).index(cap)
+    return f"k_bucket_lds<{D}, {lds_threads(c, D)}, {cap}>"
 
 
 def kmax_for(D):
@@ -68,7 +109,8 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
     """Host-side census of the work the method does on this input, routed as
     the library routes it: per record width D, the compare-exchanges of
     single-tile sub-arrays ('tiles_dD'), of tiles inside in-LDS sub-arrays
-    and the LDS bytes their merge-split phases move ('lds_dD'), and the
+    and the LDS bytes their merge-split phases move (per size class of
+    capacity C: 'lds_dD_C'), and the
     phases and bytes of the merge-split through HBM ('merge_split').
     Computed from word lengths only."""
     lens = np.diff(offsets)
@@ -100,7 +142,9 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
             if not len(lds):
                 continue
             Tc = lds_tile(T, c)
-            l = out.setdefault(f"lds_d{D}", {"ce": 0, "words": 0, "D": D, "lds_bytes": 0})
+            l = out.setdefault(f"lds_d{D}_{c}", {"ce": 0, "words": 0, "D": D, "lds_bytes": 0,
+                                                 "buckets": 0, "tile": Tc})
+            l["buckets"] += int(len(lds))
             l["ce"] += int(tile_ce(lds, Tc).sum())
             l["words"] += int(lds.sum())
             p = (lds + Tc - 1) // Tc
@@ -129,6 +173,20 @@ def cpu_info():
     return n, model
 
 
+def copy_calibration(mib):
+    """A plain copy of mib MiB, three times: each launch reads and writes
+    exactly mib MiB, so the HBM byte counters read for it give the scale
+    between counter units and bytes."""
+    import torch
+    n = mib << 20
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +196,10 @@ def main():
     ap.add_argument("--merge-threads", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true", help="skip the per-bucket launch form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph timing")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times "
+                         "(reference reading for the HBM byte counters) and exit")
     ap.add_argument("--cpu-stride", type=int, default=8,
                     help="CPU baseline samples every k-th list of the batch")
     ap.add_argument("--json-out", default="")
@@ -151,6 +213,10 @@ def main():
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path shards by list across GPUs, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     # inputs first (spawned worker processes, before the GPU is opened)
     t0 = time.time()
@@ -180,53 +246,58 @@ def main():
     tune = bs.tuning(tile, mthreads)
     stream = torch.cuda.current_stream()
     ws = bs.Workspace(bs.workspace_bytes(total, max_len, batch.R), dev)
-    timer = bs.StageTimer(max_len, stream)
+    # one set of stage events per timed step, created (and first recorded) now
+    timers = [bs.StageTimer(max_len, stream) for _ in range(max(args.steps, 1))]
 
-    def step():
+    def step(timer):
         bs.sort_batch_staged(b_t, o_t, rs_t, batch.req_start, max_len, timer, tune, ws, out=perm)
 
     for _ in range(args.warmup):
-        step()
+        step(timers[0])
     torch.cuda.synchronize()
     bs.check_device_status(ws)
 
-    # ---- timed region: K steps; HIP events between stages on the launch stream
-    stage_sum = {}
+    # ---- timed region: K steps back to back on one stream; HIP events
+    # between the stages of every step, read after the region
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-        for k, v in timer.ms().items():          # waits for this step
-            stage_sum[k] = stage_sum.get(k, 0.0) + v
+    for k in range(args.steps):
+        step(timers[k])
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    stage_sum = {}
+    for k in range(args.steps):
+        for name, v in timers[k].ms().items():
+            stage_sum[name] = stage_sum.get(name, 0.0) + v
     stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
     value = total / (ms_per_step / 1e3)
     bs.check_device_status(ws)
     got = perm.cpu().numpy()
 
     # ---- the same batch through a captured graph plan (one graph launch per step)
-    cap_req = int(np.diff(batch.req_start).max())
-    plan = bs.Plan(total, batch.R, cap_req, max_len, tune)
-    gws = bs.Workspace(plan.workspace_bytes, dev)
-    gperm = torch.empty(total, dtype=torch.int32, device=dev)
-    for _ in range(args.warmup):
-        plan.execute(b_t, o_t, rs_t, batch.req_start, gws, out=gperm)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.execute(b_t, o_t, rs_t, batch.req_start, gws, out=gperm)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    bs.check_device_status(gws)
-    g_ms = ev0.elapsed_time(ev1) / args.steps
-    graph = {"value": total / (g_ms / 1e3), "unit": "words/s", "ms_per_step": g_ms,
-             "identical": bool(np.array_equal(gperm.cpu().numpy(), got))}
-    plan.close()
-    del gws, gperm
+    graph = None
+    if not args.no_graph:
+        cap_req = int(np.diff(batch.req_start).max())
+        plan = bs.Plan(total, batch.R, cap_req, max_len, tune)
+        gws = bs.Workspace(plan.workspace_bytes, dev)
+        gperm = torch.empty(total, dtype=torch.int32, device=dev)
+        for _ in range(args.warmup):
+            plan.execute(b_t, o_t, rs_t, batch.req_start, gws, out=gperm)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            plan.execute(b_t, o_t, rs_t, batch.req_start, gws, out=gperm)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        bs.check_device_status(gws)
+        g_ms = ev0.elapsed_time(ev1) / args.steps
+        graph = {"value": total / (g_ms / 1e3), "unit": "words/s", "ms_per_step": g_ms,
+                 "identical": bool(np.array_equal(gperm.cpu().numpy(), got))}
+        plan.close()
+        del gws, gperm
 
     # ---- the plain form: one launch per (list, length) sub-array and per phase
     plain = None
@@ -246,25 +317,35 @@ def main():
                  "identical_to_batched": same}
         del pws, pperm
 
-    # ---- roofline of the dominant kernel
+    # ---- roofline of the dominant kernel (the stage with the largest time;
+    # every tile and in-LDS stage is exactly one kernel launch)
     struct, merge_bytes, phases_max = workload_structure(
         batch.offsets, batch.req_start, max_len, tile or 256, 2048)
     dom = max(stage_ms, key=stage_ms.get)
     roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": None, "traffic": None}
     if dom in struct:
-        D = struct[dom]["D"]
-        ce = struct[dom]["ce"]
+        w = struct[dom]
+        D, ce, sec = w["D"], w["ce"], stage_ms[dom] / 1e3
         ops = 3 * D * ce                       # D dword compares + 2D dword selects per CE
-        achieved = ops / (stage_ms[dom] / 1e3) / 1e12
-        kern = (f"k_bucket_lds<{D},*>" if dom.startswith("lds") else f"k_oets_tiles<{D}>")
-        roof = {"bound": "alu", "kernel": kern, "achieved": achieved,
+        achieved = ops / sec / 1e12
+        roof = {"bound": "alu", "kernel": kernel_name(dom), "achieved": achieved,
                 "peak": PEAK_INT32_TOPS, "unit": "TOP/s", "frac": achieved / PEAK_INT32_TOPS,
-                "traffic": None, "ce_per_launch": ce, "ce_per_s": ce / (stage_ms[dom] / 1e3),
-                "ops_per_ce": 3 * D}
-        if "lds_bytes" in struct[dom]:
-            roof["lds_merge_bytes"] = struct[dom]["lds_bytes"]
-            roof["lds_merge_tb_s"] = struct[dom]["lds_bytes"] / (stage_ms[dom] / 1e3) / 1e12
+                "traffic": measured_traffic(kernel_name(dom)),
+                # key lanes (8 B each) read, perm read and written (4 + 4 B) per word
+                "hbm_bytes_algorithmic": (8 * (D // 2) + 8) * w["words"],
+                "launch_ms": stage_ms[dom], "ce_per_launch": ce,
+                "ce_per_s": ce / sec, "ops_per_ce": 3 * D, "words_per_launch": w["words"]}
+        # the compare-exchange roofline as an LDS stream: each CE reads and
+        # writes two (key, index) records, 4 * 4D bytes
+        lds_ce = 16 * D * ce
+        roof["lds_ce"] = {"bytes_per_ce": 16 * D, "bytes": lds_ce,
+                          "achieved_tb_s": lds_ce / sec / 1e12, "peak_tb_s": PEAK_LDS_TBS,
+                          "frac": lds_ce / sec / 1e12 / PEAK_LDS_TBS}
+        if "lds_bytes" in w:
+            roof["merge_lds_bytes"] = w["lds_bytes"]
+            roof["floor_ms"] = (ops / (PEAK_INT32_TOPS * 1e12)
+                                + w["lds_bytes"] / (PEAK_LDS_TBS * 1e12)) * 1e3
     elif dom == "merge_split" and merge_bytes:
         achieved = merge_bytes / (stage_ms[dom] / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": "k_merge_phase", "achieved": achieved,
@@ -293,7 +374,8 @@ def main():
                   "bit_exact": bool(np.array_equal(gsub, operm))}
 
     line = {
-        "metric": "words sorted/sec (bit-exact), batched graph launch",
+        "metric": "words sorted/sec (bit-exact) batched vs per-bucket launch; "
+                  "p50/p99 request latency",
         "value": value, "unit": "words/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",

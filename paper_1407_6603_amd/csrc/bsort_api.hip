@@ -1,5 +1,6 @@
 // C ABI of libbsort: argument checks, workspace layout, launch sequences,
 // the plain per-bucket form and captured plans.  See include/bsort.h.
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -327,31 +328,57 @@ static Job batch_job(const Layout& L, char* ws, const Bounds& bd, const bsort_ba
     return j;
 }
 
-// stages: bucketize, pack, tiles_d2..tiles_d<dmax>, lds_d2..lds_d<min(5, dmax)>, merge_split
+// stages: bucketize, pack, tiles_d2..tiles_d<dmax>, then one stage per in-LDS
+// size class, lds_d<D>_<capacity> for D = 2..min(5, dmax), then merge_split
 static int stage_dmax(int32_t max_len) { return max_len >= 1 ? dwords_for_len(max_len) : 1; }
 static int stage_lds_max(int32_t max_len) { return std::min(stage_dmax(max_len), kLdsMaxD); }
+
+struct StageNames {
+    char tiles[kNumD][16];
+    char lds[kLdsMaxD + 1][kLdsClasses][24];
+    StageNames() {
+        for (int D = 0; D < kNumD; ++D) snprintf(tiles[D], sizeof tiles[D], "tiles_d%d", D);
+        for (int D = 0; D <= kLdsMaxD; ++D)
+            for (int c = 0; c < kLdsClasses; ++c)
+                snprintf(lds[D][c], sizeof lds[D][c], "lds_d%d_%d", D, lds_cap(c, D));
+    }
+};
+static const StageNames& stage_names() {
+    static const StageNames n;
+    return n;
+}
+
+// the in-LDS stages in order: (D, class) pairs
+static int lds_stages(int32_t max_len, int* Ds, int* cs) {
+    int k = 0;
+    for (int D = 2; D <= stage_lds_max(max_len); ++D)
+        for (int c = 0; c < kLdsClasses; ++c)
+            if (lds_fits(D, c)) {
+                if (Ds) Ds[k] = D;
+                if (cs) cs[k] = c;
+                ++k;
+            }
+    return k;
+}
 
 int bsort_stage_count(int32_t max_len) {
     if (max_len < 0 || max_len > BSORT_MAX_LEN) return 0;
     const int nd = stage_dmax(max_len) - 1;
-    const int nl = stage_lds_max(max_len) - 1;
-    return 3 + (nd > 0 ? nd : 0) + (nl > 0 ? nl : 0);
+    return 3 + (nd > 0 ? nd : 0) + lds_stages(max_len, nullptr, nullptr);
 }
 
 const char* bsort_stage_name(int32_t max_len, int i) {
-    static const char* kTiles[] = {"", "", "tiles_d2", "tiles_d3", "tiles_d4", "tiles_d5",
-                                   "tiles_d6", "tiles_d7", "tiles_d8", "tiles_d9", "tiles_d10",
-                                   "tiles_d11", "tiles_d12", "tiles_d13", "tiles_d14",
-                                   "tiles_d15", "tiles_d16", "tiles_d17"};
-    static const char* kLds[] = {"", "", "lds_d2", "lds_d3", "lds_d4", "lds_d5"};
     const int n = bsort_stage_count(max_len);
     if (i < 0 || i >= n) return nullptr;
     if (i == 0) return "bucketize";
     if (i == 1) return "pack";
     if (i == n - 1) return "merge_split";
     const int nd = stage_dmax(max_len) - 1;
-    if (i - 2 < nd) return kTiles[i];                  // i = 2 .. nd+1 -> D = i
-    return kLds[i - nd];                               // D = 2 ..
+    if (i - 2 < nd) return stage_names().tiles[i];     // i = 2 .. nd+1 -> D = i
+    int Ds[(kLdsMaxD + 1) * kLdsClasses], cs[(kLdsMaxD + 1) * kLdsClasses];
+    lds_stages(max_len, Ds, cs);
+    const int k = i - 2 - nd;
+    return stage_names().lds[Ds[k]][cs[k]];
 }
 
 static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
@@ -392,10 +419,12 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
         HIP_TRY(mark());
         HIP_TRY(launch_oets_tiles_one(jd, bd, D, s));
     }
-    for (int D = 2; D <= bd.dmax && D <= kLdsMaxD; ++D) {
-        HIP_TRY(mark());
-        HIP_TRY(launch_lds_buckets(jd, bd, D, s));
-    }
+    for (int D = 2; D <= bd.dmax && D <= kLdsMaxD; ++D)
+        for (int c = 0; c < kLdsClasses; ++c) {
+            if (!lds_fits(D, c)) continue;
+            HIP_TRY(mark());
+            HIP_TRY(launch_lds_class(jd, bd, D, c, s));
+        }
     HIP_TRY(mark());
     HIP_TRY(launch_merges(jd, bd, s));
     HIP_TRY(mark());

@@ -273,6 +273,7 @@ hipError_t launch_sort(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s);
+hipError_t launch_lds_class(const Job* J, const Bounds& b, int D, int c, hipStream_t s);
 hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_merge_phase(const Job* J, const Bounds& b, int phase, hipStream_t s);
 // plain per-bucket form pieces

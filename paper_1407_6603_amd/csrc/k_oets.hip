@@ -498,7 +498,7 @@ static const BucketLauncher kBucketLaunchers[kNumD] = {
     launch_bucket_d<17>};
 
 template <int D, int C>
-static void launch_lds_class(const Job* J, int64_t lb_cap, hipStream_t s) {
+static void launch_lds_class_t(const Job* J, int64_t lb_cap, hipStream_t s) {
     if constexpr (lds_fits(D, C)) {
         int64_t g = lb_cap < 1024 ? lb_cap : 1024;
         if (g < 1) g = 1;
@@ -506,24 +506,27 @@ static void launch_lds_class(const Job* J, int64_t lb_cap, hipStream_t s) {
     }
 }
 
-template <int D>
-static void launch_lds_d(const Job* J, int64_t lb_cap, hipStream_t s) {
-    launch_lds_class<D, 0>(J, lb_cap, s);
-    launch_lds_class<D, 1>(J, lb_cap, s);
-    launch_lds_class<D, 2>(J, lb_cap, s);
-    launch_lds_class<D, 3>(J, lb_cap, s);
-    launch_lds_class<D, 4>(J, lb_cap, s);
+using LdsLauncher = void (*)(const Job*, int64_t, hipStream_t);
+#define BSORT_LDS_ROW(D) \
+    {launch_lds_class_t<D, 0>, launch_lds_class_t<D, 1>, launch_lds_class_t<D, 2>, \
+     launch_lds_class_t<D, 3>, launch_lds_class_t<D, 4>}
+static const LdsLauncher kLdsLaunchers[kLdsMaxD + 1][kLdsClasses] = {
+    {}, {}, BSORT_LDS_ROW(2), BSORT_LDS_ROW(3), BSORT_LDS_ROW(4), BSORT_LDS_ROW(5)};
+#undef BSORT_LDS_ROW
+
+hipError_t launch_lds_class(const Job* J, const Bounds& b, int D, int c, hipStream_t s) {
+    if (D < 2 || D > kLdsMaxD || c < 0 || c >= kLdsClasses) return hipErrorInvalidValue;
+    if (!lds_fits(D, c)) return hipSuccess;
+    kLdsLaunchers[D][c](J, b.lb_cap, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s) {
-    switch (D) {
-        case 2: launch_lds_d<2>(J, b.lb_cap, s); break;
-        case 3: launch_lds_d<3>(J, b.lb_cap, s); break;
-        case 4: launch_lds_d<4>(J, b.lb_cap, s); break;
-        case 5: launch_lds_d<5>(J, b.lb_cap, s); break;
-        default: return hipErrorInvalidValue;
+    for (int c = 0; c < kLdsClasses; ++c) {
+        hipError_t e = launch_lds_class(J, b, D, c, s);
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s) {

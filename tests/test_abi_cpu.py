@@ -117,3 +117,24 @@ def test_python_api_fails_loudly_without_gpu():
     with pytest.raises(RuntimeError):
         bs.sort_batch(torch.zeros(4, dtype=torch.uint8), torch.zeros(2, dtype=torch.int64),
                       torch.zeros(2, dtype=torch.int64), np.array([0, 1]), 4)
+
+
+def test_stage_names(built):
+    """Stage names are host-side: one tile stage per record width, one stage
+    per in-LDS size class that fits 144 KiB, in launch order."""
+    out = _run_child(r'''
+from paper_1407_6603_amd import api
+for ml in (0, 4, 12, 20, 64, 65):
+    print(ml, " ".join(api.stage_names(ml)) if ml <= 64 else "-")
+''')
+    got = {int(l.split()[0]): l.split()[1:] for l in out.splitlines()}
+    assert got[0] == ["bucketize", "pack", "merge_split"]
+    assert got[4] == ["bucketize", "pack", "tiles_d2", "lds_d2_1024", "lds_d2_2048",
+                      "lds_d2_4096", "lds_d2_8192", "lds_d2_16384", "merge_split"]
+    lds12 = [n for n in got[12] if n.startswith("lds_")]
+    assert lds12 == ["lds_d2_1024", "lds_d2_2048", "lds_d2_4096", "lds_d2_8192", "lds_d2_16384",
+                     "lds_d3_1024", "lds_d3_2048", "lds_d3_4096", "lds_d3_8192", "lds_d3_12288",
+                     "lds_d4_1024", "lds_d4_2048", "lds_d4_4096", "lds_d4_8192", "lds_d4_9216"]
+    assert [n for n in got[20] if n.startswith("lds_d5")] == \
+        ["lds_d5_1024", "lds_d5_2048", "lds_d5_4096", "lds_d5_7168"]
+    assert [n for n in got[64] if n.startswith("tiles_")] == [f"tiles_d{d}" for d in range(2, 18)]
