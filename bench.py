@@ -173,6 +173,61 @@ def cpu_info():
     return n, model
 
 
+METRIC = "words sorted/sec (bit-exact) batched vs per-bucket launch; p50/p99 request latency"
+SERVE_DESC = ("serve: 2,000 Poisson arrivals at 2,000/s, sizes log-uniform in [1e3, 1e6] words, "
+              "plus one 4,000,000-word request at arrival 1,000; lengths 1-32, Zipf 1.0 over one "
+              "200,000-word vocabulary; 16 GB admission pool")
+
+
+def serve_run(sw, args):
+    """The serving loop on the serve workload, at wall-clock arrival times:
+    admission by a 16 GB pool, every admitted request launched as one batch
+    when one of 3 streams is free, host-to-device copies and result reads
+    included.  Returns latency percentiles, words/s and sampled parity."""
+    import torch
+    from paper_1407_6603_amd import serve
+    b = sw.batch
+    staging = serve.Staging(b.bytes, b.offsets, 32)
+    reqs = [serve.Request(i, float(sw.arrivals[i]), int(b.req_start[i]), int(b.req_start[i + 1]),
+                          int(b.offsets[b.req_start[i + 1]] - b.offsets[b.req_start[i]]))
+            for i in range(b.R)]
+    ex = serve.GpuExecutor(staging, streams=3)
+    # warm-up: first launches on each stream (library load, allocator)
+    warm = [serve.Request(r.rid, 0.0, r.first_word, r.last_word, r.n_bytes) for r in reqs[:20]]
+    serve.Server(ex, pool_bytes=16 << 30).run(warm, keep_perms=False)
+    torch.cuda.synchronize()
+    srv = serve.Server(ex, pool_bytes=16 << 30)
+    res = srv.run(reqs, keep_perms=True)
+    st = serve.latency_stats(res)
+    st.update({"batches": srv.batches, "pool_high_bytes": srv.pool_high,
+               "offered_words_per_s": float(b.total / max(sw.arrivals[-1], 1e-9)),
+               "workload": SERVE_DESC + (f" (first {b.R} arrivals)" if args.serve_arrivals else "")})
+    if not args.no_cpu_baseline:
+        import oracle
+        pick = sorted(set(list(range(0, b.R, max(b.R // 24, 1))) + [min(1000, b.R - 1)]))
+        ok = True
+        for r in pick:
+            w = b.request(r)
+            ok &= bool(np.array_equal(res[r].perm, oracle.definition_sort(w.bytes, w.offsets)))
+        st["parity"] = {"requests_checked": len(pick),
+                        "words_checked": int(sum(res[r].n for r in pick)), "bit_exact": ok,
+                        "oracle": "definition (stable sort by length, bytes, index)"}
+    return st
+
+
+def serve_line(sw, args, gen_s):
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    st = serve_run(sw, args)
+    return {"metric": METRIC, "value": st["words_per_s"], "unit": "words/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": st["span_s"] * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic", "config": {"workload": st.pop("workload")},
+            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "serving": st, "gen_seconds": gen_s}
+
+
 def copy_calibration(mib):
     """A plain copy of mib MiB, three times: each launch reads and writes
     exactly mib MiB, so the HBM byte counters read for it give the scale
@@ -197,6 +252,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the per-bucket launch form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph timing")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving run (its own JSON line)")
+    ap.add_argument("--serve-arrivals", type=int, default=0,
+                    help="serve only the first N arrivals (0: all)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(reference reading for the HBM byte counters) and exit")
@@ -220,6 +280,12 @@ def main():
 
     # inputs first (spawned worker processes, before the GPU is opened)
     t0 = time.time()
+    sw = None
+    if not args.no_serve or args.serve_only:
+        sw = wordgen.serve(workers=args.gen_workers, count=args.serve_arrivals or None)
+    if args.serve_only:
+        print(json.dumps(serve_line(sw, args, time.time() - t0)), flush=True)
+        return
     batch = wordgen.batch(workers=args.gen_workers)
     gen_s = time.time() - t0
     max_len = 12
@@ -373,9 +439,10 @@ def main():
         parity = {"lists_checked": len(idx), "words_checked": sub.total,
                   "bit_exact": bool(np.array_equal(gsub, operm))}
 
+    serving = serve_run(sw, args) if sw is not None else None
+
     line = {
-        "metric": "words sorted/sec (bit-exact) batched vs per-bucket launch; "
-                  "p50/p99 request latency",
+        "metric": METRIC,
         "value": value, "unit": "words/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
@@ -394,6 +461,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
+        "serving": serving,
         "gpu": torch.cuda.get_device_name(0),
         "gen_seconds": gen_s,
     }

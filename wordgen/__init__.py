@@ -396,6 +396,43 @@ def serve_request(i: int, n: int, spec: ServeSpec = ServeSpec()) -> Words:
     return draw_tokens(np.random.Generator(np.random.PCG64(ts)), vocab, int(n))
 
 
+def _serve_request_packed(i: int, n: int, spec: ServeSpec):
+    w = serve_request(i, n, spec)
+    return w.bytes, np.diff(w.offsets).astype(np.uint8)
+
+
+@dataclasses.dataclass
+class ServeWorkload:
+    """The serving workload: every request's words back to back (as a
+    Batch, request r = arrival r) and the arrival times in seconds."""
+    batch: Batch
+    arrivals: np.ndarray
+
+
+def serve(spec: ServeSpec = ServeSpec(), workers: Optional[int] = None,
+          count: Optional[int] = None) -> ServeWorkload:
+    """Workload 5: all arrivals of ``spec`` (the first ``count`` if given),
+    generated in ``workers`` worker processes when > 1 (same result)."""
+    times, sizes = serve_arrivals(spec)
+    if count is not None:
+        times, sizes = times[:count], sizes[:count]
+    ids = list(range(len(sizes)))
+    if workers is not None and workers > 1:
+        ctx = multiprocessing.get_context("spawn")
+        with concurrent.futures.ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+            parts = list(ex.map(_serve_request_packed, ids, [int(n) for n in sizes],
+                                [spec] * len(ids), chunksize=8))
+    else:
+        parts = [_serve_request_packed(i, int(n), spec) for i, n in zip(ids, sizes)]
+    req_start = np.zeros(len(ids) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=req_start[1:])
+    lens = np.concatenate([p[1] for p in parts]) if parts else np.zeros(0, np.uint8)
+    offsets = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    buf = np.concatenate([p[0] for p in parts]) if parts else np.zeros(0, np.uint8)
+    return ServeWorkload(Batch(buf, offsets, req_start), np.asarray(times, dtype=np.float64))
+
+
 def random_words(rng: np.random.Generator, n: int, lmin: int, lmax: int,
                  alphabet: Optional[bytes] = None) -> Words:
     """Uniform random words for edge-case tests (any byte values allowed)."""
