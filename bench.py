@@ -89,10 +89,11 @@ def lds_caps_for(D):
     return [c for c in caps if D * 4 * c <= LDS_BYTES]
 
 
-def lds_tile(tuned, cap):
+def lds_tile(tuned, cap, D):
     """Tile size inside an in-LDS sub-array of class capacity cap."""
+    target = 512 if D <= 2 else cap // 16
     t = tuned
-    while t < cap // 32 and t < 512:
+    while t < target and t < 512:
         t <<= 1
     return t
 
@@ -141,7 +142,7 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
             lo = max(lo, c)
             if not len(lds):
                 continue
-            Tc = lds_tile(T, c)
+            Tc = lds_tile(T, c, D)
             l = out.setdefault(f"lds_d{D}_{c}", {"ce": 0, "words": 0, "D": D, "lds_bytes": 0,
                                                  "buckets": 0, "tile": Tc})
             l["buckets"] += int(len(lds))

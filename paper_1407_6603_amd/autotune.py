@@ -21,7 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tune_cache.json")
 DEFAULT = (256, 256)
-TILES = (128, 256, 512, 1024)
+TILES = (128, 256, 512)
 MERGE_THREADS = (64, 128, 256, 512, 1024)
 
 

@@ -63,13 +63,16 @@ __host__ __device__ constexpr bool lds_fits(int D, int c) {
 __host__ __device__ constexpr int lds_threads(int c, int D) {
     return c <= 1 ? 256 : (c == 2 || D >= 4) ? 512 : 1024;
 }
-constexpr int kLdsMaxTile = 1024;         // tiles inside an LDS sub-array: K <= 16
+constexpr int kLdsMaxTile = 512;          // tiles inside an LDS sub-array: K <= 8
 // tile size inside an in-LDS sub-array of class capacity cap when the tiles
-// are merged: the tuned tile doubled until there are at most ~32 merge-split
-// phases (cap/32 words), capped at 512 words
-__host__ __device__ constexpr int lds_tile(int tuned, int cap) {
+// are merged.  Two-dword records sort their tiles with exact fp64 min/max
+// (two instructions per compare-exchange), so they take the largest tile;
+// wider records double the tuned tile until at most 16 merge-split phases
+// remain.  Always a power of two, at most kLdsMaxTile.
+__host__ __device__ constexpr int lds_tile(int tuned, int cap, int D) {
+    const int target = D <= 2 ? kLdsMaxTile : cap / 16;
     int t = tuned;
-    while (t < cap / 32 && t < 512) t <<= 1;
+    while (t < target && t < kLdsMaxTile) t <<= 1;
     return t;
 }
 

@@ -23,25 +23,60 @@ namespace bsort {
 constexpr int kDppWaveShl1 = 0x130;   // lane i reads lane i+1
 constexpr int kDppWaveShr1 = 0x138;   // lane i reads lane i-1
 
+// Within a tile, records start in input order (the scatter by length is
+// stable) and only adjacent records are ever exchanged, and only when the left
+// key is strictly greater; equal keys therefore never pass each other and
+// their indices stay increasing.  So the tile sort compares keys alone: the
+// result is the (key, index) order without comparing indices.
 template <int D>
-__device__ __forceinline__ void cross_lane_odd(uint32_t (&first)[D], uint32_t (&last)[D],
-                                               int lane) {
-    uint32_t rf[D], ll[D];
+__device__ __forceinline__ bool key_gt(const uint32_t (&a)[D], const uint32_t (&b)[D]) {
+    constexpr int Dk = D - 1;                       // key dwords
+    bool g;
+    if constexpr (Dk & 1) {
+        g = a[Dk - 1] > b[Dk - 1];
+    } else {
+        const uint64_t pa = ((uint64_t)a[Dk - 2] << 32) | a[Dk - 1];
+        const uint64_t pb = ((uint64_t)b[Dk - 2] << 32) | b[Dk - 1];
+        g = pa > pb;
+    }
+    constexpr int qtop = (Dk & 1) ? Dk / 2 - 1 : Dk / 2 - 2;
+#pragma unroll
+    for (int q = qtop; q >= 0; --q) {
+        const uint64_t pa = ((uint64_t)a[2 * q] << 32) | a[2 * q + 1];
+        const uint64_t pb = ((uint64_t)b[2 * q] << 32) | b[2 * q + 1];
+        g = (pa > pb) | ((pa == pb) & g);
+    }
+    return g;
+}
+
+template <int D>
+__device__ __forceinline__ void cex_key(uint32_t (&a)[D], uint32_t (&b)[D]) {
+    const bool s = key_gt<D>(a, b);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-#ifdef BSORT_XCHG_SHFL
-        rf[d] = (uint32_t)__shfl_down((int)first[d], 1, kWave);
-        ll[d] = (uint32_t)__shfl_up((int)last[d], 1, kWave);
-#else
-        rf[d] = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)first[d], kDppWaveShl1, 0xF, 0xF,
-                                                      false);
-        ll[d] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)last[d], kDppWaveShr1, 0xF, 0xF,
-                                                      false);
-#endif
+        const uint32_t x = a[d], y = b[d];
+        a[d] = s ? y : x;
+        b[d] = s ? x : y;
+    }
+}
+
+// Odd phase across lanes: lane l's last record against lane l+1's first.
+// rf/ll carry the neighbours' records between phases; the wave-edge lanes
+// (63 for rf, 0 for ll) have no source lane, keep their initial all-ones /
+// all-zeros records, and so never exchange.
+template <int D>
+__device__ __forceinline__ void cross_lane_odd(uint32_t (&first)[D], uint32_t (&last)[D],
+                                               uint32_t (&rf)[D], uint32_t (&ll)[D]) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        rf[d] = (uint32_t)__builtin_amdgcn_update_dpp((int)rf[d], (int)first[d], kDppWaveShl1,
+                                                      0xF, 0xF, false);
+        ll[d] = (uint32_t)__builtin_amdgcn_update_dpp((int)ll[d], (int)last[d], kDppWaveShr1,
+                                                      0xF, 0xF, false);
     }
     // the same pair (lane l's last, lane l+1's first) is compared on both sides
-    const bool take_right = rec_gt<D>(last, rf) && lane != kWave - 1;
-    const bool take_left = rec_gt<D>(ll, first) && lane != 0;
+    const bool take_right = key_gt<D>(last, rf);
+    const bool take_left = key_gt<D>(ll, first);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         last[d] = take_right ? rf[d] : last[d];
@@ -72,23 +107,50 @@ __device__ __forceinline__ double dmax(double a, double b) {
     asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
-__device__ __forceinline__ double dpp_f64(double x, int ctrl_is_shl, uint64_t old_bits) {
+// DPP row move of a double; lanes without a source lane keep `old`
+__device__ __forceinline__ double dpp_f64(double old, double x, bool shl) {
     const uint64_t v = (uint64_t)__double_as_longlong(x);
+    const uint64_t o = (uint64_t)__double_as_longlong(old);
     const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-    const int olo = (int)(uint32_t)old_bits, ohi = (int)(uint32_t)(old_bits >> 32);
+    const int olo = (int)(uint32_t)o, ohi = (int)(uint32_t)(o >> 32);
     int rlo, rhi;
-    if (ctrl_is_shl) {
-        rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x130, 0xF, 0xF, false);
-        rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x130, 0xF, 0xF, false);
+    if (shl) {
+        rlo = __builtin_amdgcn_update_dpp(olo, lo, kDppWaveShl1, 0xF, 0xF, false);
+        rhi = __builtin_amdgcn_update_dpp(ohi, hi, kDppWaveShl1, 0xF, 0xF, false);
     } else {
-        rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x138, 0xF, 0xF, false);
-        rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x138, 0xF, 0xF, false);
+        rlo = __builtin_amdgcn_update_dpp(olo, lo, kDppWaveShr1, 0xF, 0xF, false);
+        rhi = __builtin_amdgcn_update_dpp(ohi, hi, kDppWaveShr1, 0xF, 0xF, false);
     }
     return __longlong_as_double((long long)(((uint64_t)(uint32_t)rhi << 32) | (uint32_t)rlo));
 }
 
 template <int K>
-__device__ __forceinline__ void phases_f64(uint32_t (&r)[K][2], int nph) {
+__device__ __forceinline__ void even_f64(double (&x)[K]) {
+#pragma unroll
+    for (int k = 0; k + 1 < K; k += 2) {
+        const double lo = dmin(x[k], x[k + 1]), hi = dmax(x[k], x[k + 1]);
+        x[k] = lo;
+        x[k + 1] = hi;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void odd_f64(double (&x)[K], double& rf, double& ll) {
+    rf = dpp_f64(rf, x[0], true);                     // right neighbour's first
+    ll = dpp_f64(ll, x[K - 1], false);                // left neighbour's last
+#pragma unroll
+    for (int k = 1; k + 1 <= K - 2; k += 2) {
+        const double lo = dmin(x[k], x[k + 1]), hi = dmax(x[k], x[k + 1]);
+        x[k] = lo;
+        x[k + 1] = hi;
+    }
+    x[K - 1] = dmin(x[K - 1], rf);
+    x[0] = dmax(ll, x[0]);
+}
+
+template <int K>
+__device__ __forceinline__ void phases_f64(uint32_t (&r)[K][2], int n) {
+    const int nph = __builtin_amdgcn_readfirstlane(n);
     double x[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -97,26 +159,14 @@ __device__ __forceinline__ void phases_f64(uint32_t (&r)[K][2], int nph) {
                                : (((uint64_t)r[k][0] << 31) | r[k][1]) + kF64Bias;
         x[k] = __longlong_as_double((long long)v);
     }
-    for (int ph = 0; ph < nph; ph += 2) {
-#pragma unroll
-        for (int k = 0; k + 1 < K; k += 2) {
-            const double lo = dmin(x[k], x[k + 1]), hi = dmax(x[k], x[k + 1]);
-            x[k] = lo;
-            x[k + 1] = hi;
-        }
-        if (ph + 1 < nph) {
-            const double rf = dpp_f64(x[0], 1, kF64Inf);    // right neighbour's first
-            const double ll = dpp_f64(x[K - 1], 0, 0);      // left neighbour's last
-#pragma unroll
-            for (int k = 1; k + 1 <= K - 2; k += 2) {
-                const double lo = dmin(x[k], x[k + 1]), hi = dmax(x[k], x[k + 1]);
-                x[k] = lo;
-                x[k + 1] = hi;
-            }
-            x[K - 1] = dmin(x[K - 1], rf);
-            x[0] = dmax(ll, x[0]);
-        }
+    // +inf above every record, 0.0 below: the edge lanes never exchange
+    double rf = __longlong_as_double((long long)kF64Inf), ll = 0.0;
+    int ph = 0;
+    for (; ph + 2 <= nph; ph += 2) {
+        even_f64<K>(x);
+        odd_f64<K>(x, rf, ll);
     }
+    if (ph < nph) even_f64<K>(x);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const uint64_t v = (uint64_t)__double_as_longlong(x[k]);
@@ -132,16 +182,36 @@ __device__ __forceinline__ void phases_f64(uint32_t (&r)[K][2], int nph) {
 }
 
 template <int D, int K>
-__device__ __forceinline__ void phases_int(uint32_t (&r)[K][D], int nph, int lane) {
-    for (int ph = 0; ph < nph; ph += 2) {
+__device__ __forceinline__ void even_int(uint32_t (&r)[K][D]) {
 #pragma unroll
-        for (int k = 0; k + 1 < K; k += 2) cex<D>(r[k], r[k + 1]);          // even phase
-        if (ph + 1 < nph) {                                                  // odd phase
+    for (int k = 0; k + 1 < K; k += 2) cex_key<D>(r[k], r[k + 1]);
+}
+
+template <int D, int K>
+__device__ __forceinline__ void odd_int(uint32_t (&r)[K][D], uint32_t (&rf)[D],
+                                        uint32_t (&ll)[D]) {
 #pragma unroll
-            for (int k = 1; k + 1 <= K - 2; k += 2) cex<D>(r[k], r[k + 1]);
-            cross_lane_odd<D>(r[0], r[K - 1], lane);
-        }
+    for (int k = 1; k + 1 <= K - 2; k += 2) cex_key<D>(r[k], r[k + 1]);
+    cross_lane_odd<D>(r[0], r[K - 1], rf, ll);
+}
+
+template <int D, int K>
+__device__ __forceinline__ void phases_int(uint32_t (&r)[K][D], int n) {
+    const int nph = __builtin_amdgcn_readfirstlane(n);
+    uint32_t rf[D], ll[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        rf[d] = 0xFFFFFFFFu;
+        ll[d] = 0u;
     }
+    // pairs of phases with no branch between them, so each phase's results
+    // take the next phase's registers without copies; a last even phase if n is odd
+    int ph = 0;
+    for (; ph + 2 <= nph; ph += 2) {
+        even_int<D, K>(r);
+        odd_int<D, K>(r, rf, ll);
+    }
+    if (ph < nph) even_int<D, K>(r);
 }
 
 // ---- tile sources: where a wave's K records per lane come from and go back to
@@ -239,9 +309,9 @@ __device__ __forceinline__ void sort_tile(const Src& src, int n, int lane) {
         for (int k = 0; k < K; ++k)
             if (lane * K + k < n && r[k][0] >= kF64KeyLimit) ok = false;
         if (__all(ok)) phases_f64<K>(r, n);
-        else phases_int<D, K>(r, n, lane);
+        else phases_int<D, K>(r, n);
     } else {
-        phases_int<D, K>(r, n, lane);
+        phases_int<D, K>(r, n);
     }
     src.template store<D, K>(r, lane);
 }
@@ -311,112 +381,123 @@ __device__ __forceinline__ void lds_rec(const uint32_t* lds, int cap, int i, uin
     for (int d = 0; d < D; ++d) x[d] = lds[d * cap + i];
 }
 
-// merge path in pair (lo .. lo+na+nb): number of the first i0 outputs taken
-// from the lower tile
+// ---- merge-split phases inside LDS
+//
+// A phase pairs tiles (a, a+1), a = s&1, s&1 + 2, ...; each pair's merged
+// order is written back over the pair, the lower tile receiving the smaller
+// half.  Keys alone are compared and on equal keys the lower tile's record
+// goes first: records of equal key keep their relative order through every
+// tile sort and merge (a stable step on a contiguous window), so the lower
+// tile's copies always carry the smaller indices and this is the (key,
+// index) order.
+//
+// Work split: the outputs of a phase are cut into slots of E consecutive
+// positions; 2T is a multiple of E, so a slot lies inside one pair.  A
+// slot finds its start on the pair's merge path by binary search, then
+// merges E outputs with one dependent LDS read each.  Each thread owns S
+// slots (independent chains), stages their outputs in registers, and
+// writes them after a barrier.
+
 template <int D>
-__device__ __forceinline__ int lds_merge_path(const uint32_t* lds, int cap, int lo, int na,
-                                              int nb, int i0) {
-    int a = i0 - nb > 0 ? i0 - nb : 0;
-    int b = i0 < na ? i0 : na;
-    while (a < b) {
+__device__ __forceinline__ void lds_key(const uint32_t* lds, int cap, int i, uint32_t (&x)[D]) {
+#pragma unroll
+    for (int d = 0; d < D - 1; ++d) x[d] = lds[d * cap + i];
+    x[D - 1] = 0;
+}
+
+// number of the first `diag` outputs of the pair (lower tile at lo, T
+// records; upper at lo+T, nb records) that come from the lower tile;
+// fixed trip count (T <= 2^logT), no branches
+template <int D>
+__device__ __forceinline__ int lds_merge_path(const uint32_t* lds, int cap, int lo, int T,
+                                              int logT, int nb, int diag) {
+    int a = diag - nb > 0 ? diag - nb : 0;
+    int b = diag < T ? diag : T;
+    for (int it = 0; it <= logT; ++it) {
         const int mid = (a + b) >> 1;
+        const int ia = mid < T ? mid : T - 1;
+        const int jb0 = diag - 1 - mid;
+        const int jb = jb0 < 0 ? 0 : (jb0 < nb ? jb0 : nb - 1);
         uint32_t x[D], y[D];
-        lds_rec<D>(lds, cap, lo + mid, x);
-        lds_rec<D>(lds, cap, lo + na + (i0 - 1 - mid), y);
-        if (rec_gt<D>(y, x)) a = mid + 1;   // lower[mid] precedes upper[i0-1-mid]
-        else b = mid;
+        lds_key<D>(lds, cap, lo + ia, x);
+        lds_key<D>(lds, cap, lo + T + jb, y);
+        const bool open = a < b;
+        const bool a_first = !key_gt<D>(x, y);          // lower[mid] <= upper[diag-1-mid]
+        a = (open && a_first) ? mid + 1 : a;
+        b = (open && !a_first) ? mid : b;
     }
     return a;
 }
 
-// One output stream of a merge-split phase: consecutive output positions,
-// crossing at most one boundary between pairs of the phase.
-template <int D>
-struct MergeChain {
-    int a, lo, nb, end, ia, ib;
+// E outputs of the pair starting at output `diag`; positions are absolute:
+// lower tile [lo, ea), upper tile [ea, eb), eb <= n
+template <int D, int E>
+__device__ __forceinline__ void lds_merge_slot(const uint32_t* lds, int cap, int n, int lo,
+                                               int T, int logT, int nb, int diag,
+                                               uint32_t (&out)[E][D]) {
+    const int ia0 = lds_merge_path<D>(lds, cap, lo, T, logT, nb, diag);
+    const int ea = lo + T, eb = ea + nb;
+    int pa = lo + ia0, pb = ea + (diag - ia0);
     uint32_t ca[D], cb[D];
-
-    __device__ __forceinline__ void start(const uint32_t* lds, int cap, int n, int T, int U0,
-                                          int off, int pos) {
-        a = off + 2 * ((pos - U0) / (2 * T));          // pair holding position pos
-        lo = a * T;
-        nb = n - (a + 1) * T < T ? n - (a + 1) * T : T;
-        end = lo + T + nb;
-        ia = lds_merge_path<D>(lds, cap, lo, T, nb, pos - lo);
-        ib = pos - lo - ia;
-        lds_rec<D>(lds, cap, ia < T ? lo + ia : lo, ca);
-        lds_rec<D>(lds, cap, ib < nb ? lo + T + ib : lo, cb);
-    }
-
-    // output for position k (the previous output was k-1, or k is the start)
-    __device__ __forceinline__ void step(const uint32_t* lds, int cap, int n, int T, int k,
-                                         uint32_t (&o)[D]) {
-        if (k == end) {                                 // next pair of the phase starts here
-            a += 2;
-            lo = end;
-            nb = n - (a + 1) * T < T ? n - (a + 1) * T : T;
-            end = lo + T + nb;
-            ia = 0;
-            ib = 0;
-            lds_rec<D>(lds, cap, lo, ca);
-            lds_rec<D>(lds, cap, lo + T, cb);
-        }
-        const bool take_a = ib >= nb || (ia < T && !rec_gt<D>(ca, cb));
-        // selects as masks: keeps ca/cb/o in registers (no select of arrays)
+    lds_rec<D>(lds, cap, pa < n ? pa : n - 1, ca);
+    lds_rec<D>(lds, cap, pb < n ? pb : n - 1, cb);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        // the lower tile's record goes first unless it is exhausted or larger
+        const bool take_a = (pb >= eb) | ((pa < ea) & !key_gt<D>(ca, cb));
         const uint32_t m = take_a ? 0xFFFFFFFFu : 0u;
 #pragma unroll
-        for (int d = 0; d < D; ++d) o[d] = cb[d] ^ ((ca[d] ^ cb[d]) & m);
-        ia += take_a ? 1 : 0;
-        ib += take_a ? 0 : 1;
-        const int nxt = take_a ? (ia < T ? lo + ia : lo) : (ib < nb ? lo + T + ib : lo);
+        for (int d = 0; d < D; ++d) out[j][d] = cb[d] ^ ((ca[d] ^ cb[d]) & m);
+        pa += take_a ? 1 : 0;
+        pb += take_a ? 0 : 1;
+        int nx = take_a ? pa : pb;
+        nx = nx < n ? nx : n - 1;            // past the end: any record, never taken
         uint32_t x[D];
-        lds_rec<D>(lds, cap, nxt, x);
+        lds_rec<D>(lds, cap, nx, x);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             ca[d] = ca[d] ^ ((x[d] ^ ca[d]) & m);
             cb[d] = x[d] ^ ((cb[d] ^ x[d]) & m);
         }
     }
-};
+}
+
+// outputs per slot: the largest power of two <= min(16, CAP/NT)
+__host__ __device__ constexpr int merge_slot_outputs(int cap, int nt) {
+    const int q = cap / nt;
+    return q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : 2;
+}
 
 template <int D, int NT, int CAP>
-__device__ void lds_merge_phase(uint32_t* lds, int n, int T, int p, int s, int tid) {
-    constexpr int EMAX = (CAP + NT - 1) / NT;
-    constexpr int EH = (EMAX + 1) / 2;                // outputs per chain
+__device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, int s, int tid) {
+    constexpr int E = merge_slot_outputs(CAP, NT);        // outputs per slot
+    constexpr int S = (CAP + NT * E - 1) / (NT * E);      // slots per thread
     const int off = s & 1;
-    if (p - 2 < off) return;                          // no pair in this phase (uniform)
-    const int a_last = p - 2 - ((p - 2 - off) & 1);   // last lower tile of the phase
+    if (p - 2 < off) return;                              // no pair in this phase (uniform)
+    const int a_last = p - 2 - ((p - 2 - off) & 1);       // last lower tile of the phase
     const int U0 = off * T;
     const int U1 = (a_last + 2) * T < n ? (a_last + 2) * T : n;
-    const int E = (n + NT - 1) / NT;                  // <= EMAX since n <= CAP
-    const int k0 = tid * E < n ? tid * E : n;
-    const int k1 = k0 + E < n ? k0 + E : n;
-    const int ps = k0 > U0 ? k0 : U0;
-    const int pe = k1 < U1 ? k1 : U1;
-    const int count = pe > ps ? pe - ps : 0;
-    // two independent chains halve the dependent LDS-load chain per thread
-    const int c0 = (count + 1) / 2, c1 = count - c0;
-    const int pm = ps + c0;
-
-    uint32_t out[2 * EH][D];
-    MergeChain<D> m0, m1;
-    if (c0 > 0) m0.start(lds, CAP, n, T, U0, off, ps);
-    if (c1 > 0) m1.start(lds, CAP, n, T, U0, off, pm);
+    uint32_t out[S][E][D];
+    int pos[S];
 #pragma unroll
-    for (int j = 0; j < EH; ++j) {
-        if (j < c0) m0.step(lds, CAP, n, T, ps + j, out[j]);
-        if (j < c1) m1.step(lds, CAP, n, T, pm + j, out[EH + j]);
-    }
-    __syncthreads();                                   // every read of this phase is done
-#pragma unroll
-    for (int j = 0; j < EH; ++j) {
-        if (j < c0) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) lds[d * CAP + ps + j] = out[j][d];
+    for (int r = 0; r < S; ++r) {
+        pos[r] = U0 + (tid + r * NT) * E;
+        if (pos[r] < U1) {
+            const int a = off + (((pos[r] - U0) >> (logT + 1)) << 1);   // pair's lower tile
+            const int lo = a << logT;
+            const int nb = n - lo - T < T ? n - lo - T : T;
+            lds_merge_slot<D, E>(lds, CAP, n, lo, T, logT, nb, pos[r] - lo, out[r]);
         }
-        if (j < c1) {
+    }
+    __syncthreads();                                      // every read of this phase is done
 #pragma unroll
-            for (int d = 0; d < D; ++d) lds[d * CAP + pm + j] = out[EH + j][d];
+    for (int r = 0; r < S; ++r) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            if (pos[r] + j < U1) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) lds[d * CAP + pos[r] + j] = out[r][j][d];
+            }
         }
     }
     __syncthreads();
@@ -435,7 +516,8 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
     if (cnt > J->lb_cap) cnt = J->lb_cap;
     const LBucket* list = J->lbuckets + slot * J->lb_cap;
     const bool tiles_only = (J->flags & kFlagTilesOnly) != 0;
-    const int T = tiles_only ? J->tile_keys[D] : lds_tile(J->tile_keys[D], CAP);
+    const int T = tiles_only ? J->tile_keys[D] : lds_tile(J->tile_keys[D], CAP, D);
+    const int logT = 31 - __builtin_clz(T);               // tile sizes are powers of two
     for (int64_t bi = blockIdx.x; bi < cnt; bi += gridDim.x) {
         const LBucket bk = list[bi];
         const int n = bk.n_b;                          // T < n <= CAP (checked when listed)
@@ -460,7 +542,8 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         }
         __syncthreads();
         if (!tiles_only)
-            for (int s = 0; s < p; ++s) lds_merge_phase<D, NT, CAP>(lds, n, T, p, s, tid);
+            for (int s = 0; s < p; ++s)
+                lds_merge_phase<D, NT, CAP>(lds, n, T, logT, p, s, tid);
         for (int i = tid; i < n; i += NT) perm[i] = (int32_t)lds[Dk * CAP + i];
         __syncthreads();                               // LDS reused by the next sub-array
     }

@@ -258,9 +258,10 @@ def lds_caps(D):
     return [c for c in (1024, 2048, 4096, 8192, top) if D * 4 * c <= 144 * 1024]
 
 
-def lds_tile(tuned, cap):
+def lds_tile(tuned, cap, D):
+    target = 512 if D <= 2 else cap // 16
     t = tuned
-    while t < cap // 32 and t < 512:
+    while t < target and t < 512:
         t <<= 1
     return t
 
@@ -275,7 +276,7 @@ def test_zero_one_lds_classes(bs, ws, L):
     rng = np.random.default_rng(1000 + L)
     sizes, prev = [], T
     for cap in lds_caps(D):
-        sizes += [prev + 1, prev + lds_tile(T, cap) + 1, cap - 1, cap]
+        sizes += [prev + 1, prev + lds_tile(T, cap, D) + 1, cap - 1, cap]
         prev = cap
     sizes += [prev + 1, prev + 3 * T + 1]
     seqs = []
