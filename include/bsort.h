@@ -150,21 +150,28 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
                               void *ws, size_t ws_bytes, bsort_stream_t stream);
 
 /*
- * Stage timing.  A batch sort runs these stages in order: "bucketize",
- * "pack" (tile planning and key packing), one "tiles_d<D>" tile-sort launch
- * per record width D = 2 .. ceil(max_len/4)+1 (D = ceil(L/4)+1 for words of
- * L bytes), one "lds_d<D>_<C>" launch per in-LDS size class of capacity C
- * words for D = 2 .. min(5, ceil(max_len/4)+1) (sub-arrays sorted whole in
- * LDS; C = 1024, 2048, 4096, 8192 where D*4*C <= 144 KiB, and a largest class
- * of 16384, 12288, 9216 or 7168 words for D = 2, 3, 4, 5), and
- * "merge_split" (phases through HBM).  bsort_stage_count(max_len) is their
- * number and bsort_stage_name(max_len, i) the name of stage i (NULL if out of
- * range).  bsort_sort_batch_staged is bsort_sort_batch that also records the
- * caller's HIP events (hipEvent_t passed as void*) on the stream: events[0]
- * before the first stage and events[i+1] after stage i, so
- * hipEventElapsedTime(events[i], events[i+1]) is stage i's device time.
- * n_events must be bsort_stage_count(b->max_len) + 1.  The per-bucket form
- * cannot be staged.
+ * Stage timing.  A batch sort has these stages: "bucketize", "pack" (tile
+ * planning and key packing), one "tiles_d<D>" tile-sort launch per record
+ * width D = 2 .. ceil(max_len/4)+1 (D = ceil(L/4)+1 for words of L bytes),
+ * one "lds_d<D>_<C>" launch per in-LDS size class of capacity C words for
+ * D = 2 .. min(5, ceil(max_len/4)+1) (sub-arrays sorted whole in LDS; C =
+ * 1024, 2048, 4096, 8192 where D*4*C <= 144 KiB, and a largest class of
+ * 16384, 12288, 9216 or 7168 words for D = 2, 3, 4, 5), and "merge_split"
+ * (phases through HBM).  bsort_stage_count(max_len) is their number and
+ * bsort_stage_name(max_len, i) the name of stage i (NULL if out of range).
+ *
+ * bucketize and pack run in order on the caller's stream, then the tile
+ * stages and merge_split, in that order (merge_split merges the tiles the
+ * tile stages sort).  The in-LDS stages touch sub-arrays of their own and
+ * run concurrently with those on three library streams (default priority),
+ * joined back into the caller's stream before the call's work ends.
+ *
+ * bsort_sort_batch_staged is bsort_sort_batch that also records the caller's
+ * HIP events (hipEvent_t passed as void*): events[2i] just before stage i and
+ * events[2i+1] just after it, on the stream that runs stage i, so
+ * hipEventElapsedTime(events[2i], events[2i+1]) is stage i's device time
+ * (with other stages running beside it).  n_events must be
+ * 2 * bsort_stage_count(b->max_len).  The per-bucket form cannot be staged.
  */
 int bsort_stage_count(int32_t max_len);
 const char *bsort_stage_name(int32_t max_len, int i);

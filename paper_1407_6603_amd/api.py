@@ -168,21 +168,37 @@ def stage_names(max_len: int):
 
 
 class StageTimer:
-    """HIP events for bsort_sort_batch_staged, on one stream."""
+    """HIP events for bsort_sort_batch_staged: a begin and an end event per
+    stage, recorded on the stream that runs the stage."""
 
     def __init__(self, max_len: int, stream=None):
         self.names = stage_names(max_len)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(len(self.names) + 1)]
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(self.names))]
         for e in self.events:              # torch creates the HIP event on first record
             e.record(self.stream)
         self.handles = (ctypes.c_void_p * len(self.events))(*[e.cuda_event for e in self.events])
 
     def ms(self):
         """Per-stage device milliseconds of the last staged sort (waits for it)."""
-        self.events[-1].synchronize()
-        return {n: self.events[i].elapsed_time(self.events[i + 1])
+        for e in self.events:
+            e.synchronize()
+        return {n: self.events[2 * i].elapsed_time(self.events[2 * i + 1])
                 for i, n in enumerate(self.names)}
+
+    def span_ms(self, pick):
+        """Milliseconds from the earliest start to the latest end of the
+        stages whose names satisfy pick (stages may overlap)."""
+        idx = [i for i, n in enumerate(self.names) if pick(n)]
+        if not idx:
+            return 0.0
+        ref = self.events[0]
+        ref.synchronize()
+        for e in self.events:
+            e.synchronize()
+        t0 = min(ref.elapsed_time(self.events[2 * i]) for i in idx)
+        t1 = max(ref.elapsed_time(self.events[2 * i + 1]) for i in idx)
+        return t1 - t0
 
 
 def sort_batch_staged(bytes_t, offsets_t, req_start_t, h_req_start, max_len: int,

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -260,6 +261,9 @@ bsort_status bsort_bucketize(const bsort_words* w, const bsort_buckets* b, void*
     return BSORT_OK;
 }
 
+static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
+                               void* const* ev);
+
 bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, int32_t* perm,
                                 const bsort_tuning* t, void* ws, size_t ws_bytes,
                                 bsort_stream_t stream) {
@@ -283,7 +287,7 @@ bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, in
     j.order = b->order;
     j.perm = perm;
     HIP_TRY(launch_set_job(j, jd, s));
-    HIP_TRY(launch_sort(jd, bd, s));
+    HIP_TRY(enqueue_sort(jd, bd, s, false, nullptr));
     return BSORT_OK;
 }
 
@@ -381,6 +385,130 @@ const char* bsort_stage_name(int32_t max_len, int i) {
     return stage_names().lds[Ds[k]][cs[k]];
 }
 
+// ---- concurrent sort stages
+//
+// After the key pack the sort stages fall into independent groups: the
+// in-LDS size classes each sort sub-arrays of their own, while the
+// register-tile sorts must precede the merge-split phases through HBM (those
+// merge tiles the tile sorts made).  The tile sorts and the merge-split run
+// in order on the caller's stream; the in-LDS classes, largest first, go
+// round-robin onto kFan-1 library streams of default priority between a
+// fork and a join event, so the last partial round of one stage overlaps the
+// others.  Library streams come from a few pools per device, picked by the
+// caller's stream; a pool is locked while a call enqueues (its events are
+// reused), and graph capture forks and joins the same way.
+constexpr int kFan = 4;
+constexpr int kFanPools = 4;
+constexpr int kMaxDevices = 64;
+
+struct FanPool {
+    std::mutex mu;
+    bool ready = false;
+    hipStream_t aux[kFan - 1] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kFan - 1] = {};
+};
+
+static FanPool g_fan[kMaxDevices][kFanPools];
+
+// caller streams get pools round-robin in order of first use, so a few
+// streams working side by side do not queue behind each other
+static int fan_pool_for(int dev, hipStream_t s) {
+    static std::mutex mu;
+    static std::vector<std::pair<hipStream_t, int>> seen[kMaxDevices];
+    static int next[kMaxDevices];
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto& kv : seen[dev])
+        if (kv.first == s) return kv.second;
+    const int k = next[dev]++ % kFanPools;
+    if (seen[dev].size() < 256) seen[dev].push_back({s, k});
+    return k;
+}
+
+static hipError_t fan_init(FanPool& f) {
+    if (f.ready) return hipSuccess;
+    hipError_t e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming);
+    for (int k = 0; k < kFan - 1 && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&f.aux[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&f.join[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) f.ready = true;
+    return e;
+}
+
+enum StageKind { kStageTiles, kStageLds, kStageMerge };
+struct StageRef {
+    int kind, D, c, index;   // index: position in bsort_stage_name order
+};
+
+// the sort stages after the pack: lane 0 (caller's stream) holds the tile
+// sorts then the merge-split; the in-LDS classes follow, largest first
+static std::vector<StageRef> sort_stages(const Bounds& b) {
+    const int nd = b.dmax - 1;
+    std::vector<StageRef> v;
+    int Ds[(kLdsMaxD + 1) * kLdsClasses], cs[(kLdsMaxD + 1) * kLdsClasses];
+    const int nl = lds_stages(b.ml1 - 1, Ds, cs);
+    for (int D = 2; D <= b.dmax && D <= kMaxD; ++D) v.push_back({kStageTiles, D, 0, D});
+    v.push_back({kStageMerge, 0, 0, 2 + nd + nl});    // merge_split is the last stage name
+    for (int c = kLdsClasses - 1; c >= 0; --c)
+        for (int k = 0; k < nl; ++k)
+            if (cs[k] == c) v.push_back({kStageLds, Ds[k], c, 2 + nd + k});
+    return v;
+}
+
+static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, hipStream_t s) {
+    switch (st.kind) {
+        case kStageTiles: return launch_oets_tiles_one(J, b, st.D, s);
+        case kStageLds: return launch_lds_class(J, b, st.D, st.c, s);
+        default: return launch_merges(J, b, s);
+    }
+}
+
+// Everything after the job descriptor: bucketize (if asked), prep and pack on
+// the caller's stream, then the sort stages fanned out and joined back.
+// ev (optional): 2 events per stage in bsort_stage_name order, recorded just
+// before and after the stage on the stream that runs it.
+static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
+                               void* const* ev) {
+    auto rec = [&](int i, int end, hipStream_t x) -> hipError_t {
+        return ev ? hipEventRecord((hipEvent_t)ev[2 * i + end], x) : hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    if (bucketize) {
+        if ((e = rec(0, 0, s)) != hipSuccess) return e;
+        if ((e = launch_bucketize(J, b, s)) != hipSuccess) return e;
+        if ((e = rec(0, 1, s)) != hipSuccess) return e;
+    }
+    if ((e = rec(1, 0, s)) != hipSuccess) return e;
+    if ((e = launch_sort_prep(J, b, s)) != hipSuccess) return e;
+    if ((e = rec(1, 1, s)) != hipSuccess) return e;
+
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    FanPool& f = g_fan[dev][fan_pool_for(dev, s)];
+    std::lock_guard<std::mutex> lock(f.mu);
+    if ((e = fan_init(f)) != hipSuccess) return e;
+    hipStream_t st[kFan] = {s, f.aux[0], f.aux[1], f.aux[2]};
+    if ((e = hipEventRecord(f.fork, s)) != hipSuccess) return e;
+    for (int k = 1; k < kFan; ++k)
+        if ((e = hipStreamWaitEvent(st[k], f.fork, 0)) != hipSuccess) return e;
+    const std::vector<StageRef> stages = sort_stages(b);
+    int lds_seen = 0;
+    for (size_t i = 0; i < stages.size(); ++i) {
+        // tiles then merge-split stay in order on the caller's stream
+        hipStream_t x = stages[i].kind == kStageLds ? st[1 + (lds_seen++) % (kFan - 1)] : s;
+        if ((e = rec(stages[i].index, 0, x)) != hipSuccess) return e;
+        if ((e = run_stage(stages[i], J, b, x)) != hipSuccess) return e;
+        if ((e = rec(stages[i].index, 1, x)) != hipSuccess) return e;
+    }
+    for (int k = 1; k < kFan; ++k) {
+        if ((e = hipEventRecord(f.join[k - 1], st[k])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, f.join[k - 1], 0)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
 static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
                                     void* ws, size_t ws_bytes, bsort_stream_t stream,
                                     void* const* events, int n_events) {
@@ -389,8 +517,8 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
     if (st != BSORT_OK) return st;
     if ((st = check_tuning(t)) != BSORT_OK) return st;
     if (events) {
-        if (n_events != bsort_stage_count(b->max_len) + 1)
-            return fail(BSORT_E_INVALID, "n_events must be bsort_stage_count(max_len) + 1");
+        if (n_events != 2 * bsort_stage_count(b->max_len))
+            return fail(BSORT_E_INVALID, "n_events must be 2 * bsort_stage_count(max_len)");
         for (int i = 0; i < n_events; ++i)
             if (!events[i]) return fail(BSORT_E_INVALID, "an event is NULL");
         if (t && (t->flags & BSORT_FLAG_PER_BUCKET_LAUNCH))
@@ -406,28 +534,8 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
     Bounds bd = make_bounds(L, total, b->n_requests, n_max, t);
     Job* jd = (Job*)((char*)ws + L.job);
     Job j = batch_job(L, (char*)ws, bd, b, total, perm);
-    int k = 0;
-    auto mark = [&]() -> hipError_t {
-        return events ? hipEventRecord((hipEvent_t)events[k++], s) : hipSuccess;
-    };
     HIP_TRY(launch_set_job(j, jd, s));
-    HIP_TRY(mark());
-    HIP_TRY(launch_bucketize(jd, bd, s));
-    HIP_TRY(mark());
-    HIP_TRY(launch_sort_prep(jd, bd, s));
-    for (int D = 2; D <= bd.dmax && D <= kMaxD; ++D) {
-        HIP_TRY(mark());
-        HIP_TRY(launch_oets_tiles_one(jd, bd, D, s));
-    }
-    for (int D = 2; D <= bd.dmax && D <= kLdsMaxD; ++D)
-        for (int c = 0; c < kLdsClasses; ++c) {
-            if (!lds_fits(D, c)) continue;
-            HIP_TRY(mark());
-            HIP_TRY(launch_lds_class(jd, bd, D, c, s));
-        }
-    HIP_TRY(mark());
-    HIP_TRY(launch_merges(jd, bd, s));
-    HIP_TRY(mark());
+    HIP_TRY(enqueue_sort(jd, bd, s, true, events));
     return BSORT_OK;
 }
 
@@ -479,8 +587,7 @@ bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = launch_bucketize(p->job_dev, p->bd, cs);
-        if (e1 == hipSuccess) e1 = launch_sort(p->job_dev, p->bd, cs);
+        hipError_t e1 = enqueue_sort(p->job_dev, p->bd, cs, true, nullptr);
         e = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = e1;
     }

@@ -272,7 +272,6 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
 hipError_t launch_set_job(const Job& j, Job* dst, hipStream_t s);
 hipError_t launch_bucketize(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_chunk_plan(const Job* J, bool clear_status, hipStream_t s);
-hipError_t launch_sort(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s);

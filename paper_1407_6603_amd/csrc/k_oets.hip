@@ -462,10 +462,10 @@ __device__ __forceinline__ void lds_merge_slot(const uint32_t* lds, int cap, int
     }
 }
 
-// outputs per slot: the largest power of two <= min(16, CAP/NT)
+// outputs per slot: the largest power of two <= min(8, CAP/NT)
 __host__ __device__ constexpr int merge_slot_outputs(int cap, int nt) {
     const int q = cap / nt;
-    return q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : 2;
+    return q >= 8 ? 8 : q >= 4 ? 4 : 2;
 }
 
 template <int D, int NT, int CAP>

@@ -463,20 +463,4 @@ hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t launch_sort(const Job* J, const Bounds& b, hipStream_t s) {
-    hipError_t e = launch_sort_prep(J, b, s);
-    if (e != hipSuccess) return e;
-    for (int D = 2; D <= b.dmax && D <= kMaxD; ++D) {
-        e = launch_oets_tiles_one(J, b, D, s);
-        if (e != hipSuccess) return e;
-    }
-    for (int D = 2; D <= b.dmax && D <= kLdsMaxD; ++D) {
-        e = launch_lds_buckets(J, b, D, s);
-        if (e != hipSuccess) return e;
-    }
-    e = launch_merges(J, b, s);
-    if (e != hipSuccess) return e;
-    return hipGetLastError();
-}
-
 }  // namespace bsort
