@@ -98,6 +98,15 @@ def lds_tile(tuned, cap, D):
     return t
 
 
+def hbm_chunk(D):
+    """Tile of sub-arrays merged through HBM for record widths with in-LDS
+    classes: the largest power of two whose pair of tiles fits 144 KiB."""
+    c = 8192
+    while c > 128 and 2 * c * 4 * D > LDS_BYTES:
+        c >>= 1
+    return c
+
+
 def tile_ce(n, T):
     """Compare-exchanges of odd-even transposition sorts of n words cut into
     tiles of T: n_t(n_t-1)/2 per tile."""
@@ -126,7 +135,7 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
         D = (L + 3) // 4 + 1
         W = (L + 7) // 8
         T = min(tile_keys, 64 * kmax_for(D), 1024)
-        Th = min(hbm_tile_keys, 64 * kmax_for(D))
+        Th = hbm_chunk(D) if D <= 5 else min(hbm_tile_keys, 64 * kmax_for(D))
         caps = lds_caps_for(D)
         cap = max(caps) if caps else 0
         n = counts[:, L].astype(np.int64)

@@ -86,13 +86,15 @@ typedef struct {
 typedef struct {
     int32_t tile_keys;       /* words per odd-even transposition tile for sub-arrays sorted
                                 in one tile or in LDS: a power of two in [128, 4096],
-                                clamped to 1024 and per key width */
-    int32_t merge_threads;   /* threads per HBM merge-split workgroup: 64..1024, multiple
-                                of 64 */
+                                clamped to 512 and per key width */
+    int32_t merge_threads;   /* threads per merge-split workgroup of the plain form:
+                                64..1024, multiple of 64 */
     int32_t flags;           /* BSORT_FLAG_* */
     int32_t hbm_tile_keys;   /* tile size for sub-arrays too large for LDS, merged
-                                through HBM: a power of two in [128, 4096], clamped per
-                                key width and LDS size */
+                                through HBM: a power of two in [128, 8192].  Default (0):
+                                the largest tile whose pair fits LDS (8192 words for
+                                keys of up to 4 bytes, 4096 up to 12, 2048 up to 16) and
+                                2048 for longer keys; clamped per key width and LDS size */
 } bsort_tuning;
 
 /* The plain form: one kernel launch per (request, length) sub-array and per

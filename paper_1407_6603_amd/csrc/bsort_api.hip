@@ -39,7 +39,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // size a caller asks for and the layout a call uses always agree.
 struct Layout {
     size_t status, job, chunk_begin, chunk_hist, key_off, keys, tiles[kNumD], tile_count,
-        mlist[2], mcount, counts, starts, order, jobs, lbuckets, lb_count;
+        mlist[2], mcount, counts, starts, order, jobs, lbuckets, lb_count,
+        hchunks[kLdsMaxD + 1], hc_count, pmax;
     int64_t chunk_cap, tile_cap, merge_cap, lb_cap;
     int32_t phase_cap, ml1, dmax, wmax;
     size_t bytes;
@@ -74,6 +75,10 @@ bool make_layout(int64_t total, int32_t R, int32_t max_len, Layout& L) {
     L.lb_cap = 4 * (int64_t)R + 1;                    // a width class covers 4 lengths per list
     L.lbuckets = take(sizeof(LBucket) * (size_t)L.lb_cap * (kLdsMaxD + 1) * kLdsClasses);
     L.lb_count = take(sizeof(int32_t) * kNumD * kLdsClasses);
+    for (int D = 2; D <= L.dmax && D <= kLdsMaxD; ++D)
+        L.hchunks[D] = take(sizeof(LBucket) * (size_t)L.tile_cap);
+    L.hc_count = take(sizeof(int32_t) * (kLdsMaxD + 1));
+    L.pmax = take(sizeof(int32_t));
     L.mlist[0] = take(sizeof(MergeItem) * (size_t)L.merge_cap);
     L.mlist[1] = take(sizeof(MergeItem) * (size_t)L.merge_cap);
     L.mcount = take(sizeof(int32_t) * ((size_t)L.phase_cap + 1));
@@ -92,8 +97,8 @@ bsort_status check_tuning(const bsort_tuning* t) {
     if (t->tile_keys != 0 && (!pow2(t->tile_keys) || t->tile_keys < kMinTile || t->tile_keys > 4096))
         return fail(BSORT_E_INVALID, "tile_keys must be 0 or a power of two in [128, 4096]");
     if (t->hbm_tile_keys != 0 &&
-        (!pow2(t->hbm_tile_keys) || t->hbm_tile_keys < kMinTile || t->hbm_tile_keys > 4096))
-        return fail(BSORT_E_INVALID, "hbm_tile_keys must be 0 or a power of two in [128, 4096]");
+        (!pow2(t->hbm_tile_keys) || t->hbm_tile_keys < kMinTile || t->hbm_tile_keys > 8192))
+        return fail(BSORT_E_INVALID, "hbm_tile_keys must be 0 or a power of two in [128, 8192]");
     if (t->merge_threads != 0 &&
         (t->merge_threads < 64 || t->merge_threads > 1024 || t->merge_threads % 64))
         return fail(BSORT_E_INVALID, "merge_threads must be 0 or a multiple of 64 in [64, 1024]");
@@ -114,7 +119,6 @@ Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
     b.dmax = L.dmax;
     b.flags = t ? t->flags : 0;
     const int want = (t && t->tile_keys) ? t->tile_keys : kDefaultTile;
-    const int want_hbm = (t && t->hbm_tile_keys) ? t->hbm_tile_keys : kDefaultHbmTile;
     const int budget = merge_lds_budget();
     int need = 0;
     int64_t pb = 0;
@@ -122,16 +126,30 @@ Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
         // single tiles and tiles inside in-LDS sub-arrays
         int T = std::min(std::min(want, kWave * kmax_for(D)), kLdsMaxTile);
         b.tile_keys[D] = T;
-        // sub-arrays too large for LDS: tiles merged through HBM, both tiles in LDS
-        int Th = std::min(want_hbm, kWave * kmax_for(D));
-        while (Th > kMinTile && D * 2 * Th * 4 > budget) Th >>= 1;
+        // sub-arrays too large for LDS, merged through HBM.  Batched form:
+        // chunks of the largest power of two whose pair fits LDS, sorted by
+        // an in-LDS class (D <= kLdsMaxD), else register-sized tiles.  The
+        // plain form keeps register tiles whose pairs it merges in LDS.
+        const int want_h = (t && t->hbm_tile_keys) ? t->hbm_tile_keys : 0;
+        int Tp = std::min(want_h ? want_h : kDefaultHbmTile, kWave * kmax_for(D));
+        while (Tp > kMinTile && D * 2 * Tp * 4 > budget) Tp >>= 1;
+        b.plain_tile_keys[D] = Tp;
+        int Th;
+        if (D <= kLdsMaxD) {
+            Th = hbm_chunk_max(D);
+            if (want_h && want_h < Th) Th = want_h;
+            b.hbm_class[D] = hbm_chunk_class(D, Th);
+        } else {
+            Th = std::min(want_h ? want_h : kDefaultHbmTile, kWave * kmax_for(D));
+            b.hbm_class[D] = -1;
+        }
         b.hbm_tile_keys[D] = Th;
         if (D > L.dmax) continue;
         int cap = 0;                                   // largest in-LDS sub-array for D
         for (int c = 0; c < kLdsClasses; ++c)
             if (lds_fits(D, c)) cap = std::max(cap, lds_cap(c, D));
         if (n_max > std::max(cap, T)) {                // some sub-array may take the HBM path
-            need = std::max(need, D * 2 * Th * 4);
+            need = std::max(need, D * 2 * Tp * 4);
             pb = std::max<int64_t>(pb, (n_max + Th - 1) / Th);
         }
     }
@@ -140,6 +158,7 @@ Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
     b.merge_lds = std::max(1024, std::min(budget, 2 * need));
     b.lb_cap = L.lb_cap;
     b.phase_bound = (int32_t)std::min<int64_t>(pb, L.phase_cap);
+    b.pair_lds = pair_merge_lds(L.dmax);
     return b;
 }
 
@@ -164,6 +183,9 @@ Job base_job(const Layout& L, char* ws, const Bounds& b) {
         j.tile_keys[D] = b.tile_keys[D];
         j.hbm_tile_keys[D] = b.hbm_tile_keys[D];
     }
+    for (int D = 2; D <= L.dmax && D <= kLdsMaxD; ++D) j.hchunks[D] = (LBucket*)(ws + L.hchunks[D]);
+    j.hc_count = (int32_t*)(ws + L.hc_count);
+    j.pmax = (int32_t*)(ws + L.pmax);
     j.lbuckets = (LBucket*)(ws + L.lbuckets);
     j.lb_count = (int32_t*)(ws + L.lb_count);
     j.lb_cap = L.lb_cap;
@@ -262,7 +284,7 @@ bsort_status bsort_bucketize(const bsort_words* w, const bsort_buckets* b, void*
 }
 
 static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
-                               void* const* ev);
+                               void* const* ev, const int32_t* d_pmax);
 
 bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, int32_t* perm,
                                 const bsort_tuning* t, void* ws, size_t ws_bytes,
@@ -287,7 +309,7 @@ bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, in
     j.order = b->order;
     j.perm = perm;
     HIP_TRY(launch_set_job(j, jd, s));
-    HIP_TRY(enqueue_sort(jd, bd, s, false, nullptr));
+    HIP_TRY(enqueue_sort(jd, bd, s, false, nullptr, j.pmax));
     return BSORT_OK;
 }
 
@@ -407,6 +429,8 @@ struct FanPool {
     hipStream_t aux[kFan - 1] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kFan - 1] = {};
+    hipEvent_t pmax_ev = nullptr;   // the merge-split phase count has reached the host
+    int32_t* host_pmax = nullptr;   // pinned
 };
 
 static FanPool g_fan[kMaxDevices][kFanPools];
@@ -432,8 +456,22 @@ static hipError_t fan_init(FanPool& f) {
         e = hipStreamCreateWithFlags(&f.aux[k], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.join[k], hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f.pmax_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&f.host_pmax, sizeof(int32_t), 0);
     if (e == hipSuccess) f.ready = true;
     return e;
+}
+
+// set up the pool a stream will use (allocations are not allowed while a
+// stream is being captured, so plans call this before capturing)
+static hipError_t fan_prepare(hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    FanPool& f = g_fan[dev][fan_pool_for(dev, s)];
+    std::lock_guard<std::mutex> lock(f.mu);
+    return fan_init(f);
 }
 
 enum StageKind { kStageTiles, kStageLds, kStageMerge };
@@ -456,20 +494,25 @@ static std::vector<StageRef> sort_stages(const Bounds& b) {
     return v;
 }
 
-static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, hipStream_t s) {
+static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, hipStream_t s,
+                            int phases) {
     switch (st.kind) {
         case kStageTiles: return launch_oets_tiles_one(J, b, st.D, s);
         case kStageLds: return launch_lds_class(J, b, st.D, st.c, s);
-        default: return launch_merges(J, b, s);
+        default: return launch_merges(J, b, phases, s);
     }
 }
 
 // Everything after the job descriptor: bucketize (if asked), prep and pack on
 // the caller's stream, then the sort stages fanned out and joined back.
 // ev (optional): 2 events per stage in bsort_stage_name order, recorded just
-// before and after the stage on the stream that runs it.
+// before and after the stage on the stream that runs it.  d_pmax (optional):
+// the job's device word holding the most merge-split phases any sub-array
+// needs; outside graph capture it is read back once the plan is made (the
+// in-LDS classes already running) so exactly that many phases are launched
+// instead of the bound from the largest list.
 static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
-                               void* const* ev) {
+                               void* const* ev, const int32_t* d_pmax) {
     auto rec = [&](int i, int end, hipStream_t x) -> hipError_t {
         return ev ? hipEventRecord((hipEvent_t)ev[2 * i + end], x) : hipSuccess;
     };
@@ -483,24 +526,49 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     if ((e = launch_sort_prep(J, b, s)) != hipSuccess) return e;
     if ((e = rec(1, 1, s)) != hipSuccess) return e;
 
+    bool readback = false;
+    if (d_pmax && b.phase_bound > 4 && !(b.flags & kFlagTilesOnly)) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return e;
+        readback = cs == hipStreamCaptureStatusNone;
+    }
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     FanPool& f = g_fan[dev][fan_pool_for(dev, s)];
     std::lock_guard<std::mutex> lock(f.mu);
     if ((e = fan_init(f)) != hipSuccess) return e;
+    if (readback) {
+        if ((e = hipMemcpyAsync(f.host_pmax, d_pmax, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                s)) != hipSuccess)
+            return e;
+        if ((e = hipEventRecord(f.pmax_ev, s)) != hipSuccess) return e;
+    }
     hipStream_t st[kFan] = {s, f.aux[0], f.aux[1], f.aux[2]};
     if ((e = hipEventRecord(f.fork, s)) != hipSuccess) return e;
     for (int k = 1; k < kFan; ++k)
         if ((e = hipStreamWaitEvent(st[k], f.fork, 0)) != hipSuccess) return e;
     const std::vector<StageRef> stages = sort_stages(b);
+    // in-LDS classes first, round-robin on the library streams
     int lds_seen = 0;
-    for (size_t i = 0; i < stages.size(); ++i) {
-        // tiles then merge-split stay in order on the caller's stream
-        hipStream_t x = stages[i].kind == kStageLds ? st[1 + (lds_seen++) % (kFan - 1)] : s;
-        if ((e = rec(stages[i].index, 0, x)) != hipSuccess) return e;
-        if ((e = run_stage(stages[i], J, b, x)) != hipSuccess) return e;
-        if ((e = rec(stages[i].index, 1, x)) != hipSuccess) return e;
+    for (const StageRef& g : stages) {
+        if (g.kind != kStageLds) continue;
+        hipStream_t x = st[1 + (lds_seen++) % (kFan - 1)];
+        if ((e = rec(g.index, 0, x)) != hipSuccess) return e;
+        if ((e = run_stage(g, J, b, x, -1)) != hipSuccess) return e;
+        if ((e = rec(g.index, 1, x)) != hipSuccess) return e;
+    }
+    // tile sorts, then the merge-split, in order on the caller's stream
+    for (const StageRef& g : stages) {
+        if (g.kind == kStageLds) continue;
+        int phases = -1;
+        if (g.kind == kStageMerge && readback) {
+            if ((e = hipEventSynchronize(f.pmax_ev)) != hipSuccess) return e;
+            phases = *f.host_pmax;
+        }
+        if ((e = rec(g.index, 0, s)) != hipSuccess) return e;
+        if ((e = run_stage(g, J, b, s, phases)) != hipSuccess) return e;
+        if ((e = rec(g.index, 1, s)) != hipSuccess) return e;
     }
     for (int k = 1; k < kFan; ++k) {
         if ((e = hipEventRecord(f.join[k - 1], st[k])) != hipSuccess) return e;
@@ -535,7 +603,7 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
     Job* jd = (Job*)((char*)ws + L.job);
     Job j = batch_job(L, (char*)ws, bd, b, total, perm);
     HIP_TRY(launch_set_job(j, jd, s));
-    HIP_TRY(enqueue_sort(jd, bd, s, true, events));
+    HIP_TRY(enqueue_sort(jd, bd, s, true, events, j.pmax));
     return BSORT_OK;
 }
 
@@ -585,9 +653,10 @@ bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap
     }
     e = hipSuccess;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = fan_prepare(cs);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = enqueue_sort(p->job_dev, p->bd, cs, true, nullptr);
+        hipError_t e1 = enqueue_sort(p->job_dev, p->bd, cs, true, nullptr, nullptr);
         e = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = e1;
     }
@@ -739,7 +808,7 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
             start += nb;
             if (l == 0 || nb < 2) continue;
             const int D = dwords_for_len(l);
-            const int T = bd0.hbm_tile_keys[D];
+            const int T = bd0.plain_tile_keys[D];
             const int nt = (nb + T - 1) / T;
             TileDesc td;
             td.pos0 = pos0;

@@ -76,8 +76,21 @@ __host__ __device__ constexpr int lds_tile(int tuned, int cap, int D) {
     return t;
 }
 
-// queue control words (Job.qctl)
-enum { Q_HEAD = 0, Q_TAIL = 1, Q_TOTAL = 2, Q_ABORT = 3, Q_ARR = 4, Q_WORDS = 8 };
+// Sub-arrays merged through HBM: tiles of the largest power of two C whose
+// pair (2C records of 4D bytes) fits the LDS budget, at most 8192 words;
+// records wider than kLdsMaxD dwords keep register-sized tiles (set on the
+// host).  hbm_pair_cap(D) = 2C is the pair merge's LDS capacity in records.
+__host__ __device__ constexpr int hbm_chunk_max(int D) {
+    int c = 8192;
+    while (c > 128 && 2 * c * 4 * D > kLdsBytes) c >>= 1;
+    return c;
+}
+// in-LDS class that sorts chunks of up to C words of width D (-1: none)
+__host__ __device__ constexpr int hbm_chunk_class(int D, int C) {
+    for (int c = 0; c < kLdsClasses; ++c)
+        if (lds_fits(D, c) && lds_cap(c, D) >= C) return c;
+    return -1;
+}
 
 // records per lane limit by key width: D * K <= 128 VGPRs of record state
 __host__ __device__ constexpr int kmax_for(int D) {
@@ -100,11 +113,13 @@ struct TileDesc {            // one odd-even transposition tile
     int32_t L;               // word length
 };
 
-struct LBucket {             // a sub-array sorted entirely in LDS
-    int64_t pos0;
-    int64_t key_off;
-    int32_t n_b;
-    int32_t L;
+struct LBucket {             // a sub-array (or a chunk of one) sorted entirely in LDS
+    int64_t pos0;            // global position of the first word
+    int64_t key_off;         // uint64 index of the first word's lane 0
+    int32_t n_b;             // words
+    int32_t L;               // word length
+    int32_t stride;          // lane stride of the key layout (the whole sub-array's size)
+    int32_t wk;              // nonzero: write the sorted keys back (a chunk merged later)
 };
 
 struct MergeItem {           // merge-split of tiles a and a+1 of a bucket at phase s
@@ -150,18 +165,16 @@ struct Job {
     LBucket* lbuckets;           // [kNumD * kLdsClasses][lb_cap]
     int32_t* lb_count;           // [kNumD * kLdsClasses]
     int64_t lb_cap;
+    // chunks of sub-arrays merged through HBM, sorted in LDS first (D <= kLdsMaxD)
+    LBucket* hchunks[kLdsMaxD + 1];   // [tile_cap[D]] each
+    int32_t* hc_count;           // [kLdsMaxD + 1]
+    int32_t* pmax;               // [1] most merge-split phases any sub-array needs
     // per-phase merge-split lists (phase s reads mlist[s&1], queues into the other)
     MergeItem* mlist[2];
     int64_t merge_cap;
     int32_t* mcount;             // [phase_cap + 1]
     int32_t phase_cap;
     int32_t pad0;
-    // dataflow merge-split scheduler
-    MergeItem* ring;             // [ring_cap] ready items
-    int64_t* ring_seq;           // [ring_cap] 2t+1: holds ticket t; 2t+2: ticket t consumed
-    int64_t ring_cap;
-    int32_t* arr;                // [ring_cap] arrivals per (bucket, pair) slot
-    int64_t* qctl;               // [Q_WORDS] head, tail, total, abort, pair-slot allocator
     int64_t rs_inline[2];        // req_start storage for single-list calls
     int64_t cb_inline[2];        // chunk_begin storage for the plain form's per-list jobs
 };
@@ -250,6 +263,17 @@ __device__ __forceinline__ void cex(uint32_t (&a)[D], uint32_t (&b)[D]) {
     }
 }
 
+// queue a merge item for phase s1
+__device__ __forceinline__ void push_item(const Job* J, int s1, const MergeItem& m) {
+    if (s1 >= J->phase_cap) {
+        set_status(J, ST_OVERFLOW);
+        return;
+    }
+    const int slot = atomicAdd(&J->mcount[s1], 1);
+    if (slot < J->merge_cap) J->mlist[s1 & 1][slot] = m;
+    else set_status(J, ST_OVERFLOW);
+}
+
 // ---------------------------------------------------------------- launchers
 
 struct Bounds {              // launch sizes fixed on the host (capacities)
@@ -258,13 +282,15 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
     int32_t ml1;
     int64_t chunk_cap;
     int64_t tile_cap;        // tile list capacity per record width
-    int64_t ring_cap;
     int32_t dmax;            // widest record in use
     int32_t phase_bound;     // merge-split phase launches
-    int32_t merge_threads;
-    int32_t merge_lds;       // dynamic LDS bytes per merge workgroup
+    int32_t merge_threads;   // plain form's merge workgroup size
+    int32_t merge_lds;       // plain form's dynamic LDS bytes per merge workgroup
+    int32_t pair_lds;        // dynamic LDS bytes of the batched pair merge
     int32_t tile_keys[kNumD];
     int32_t hbm_tile_keys[kNumD];
+    int32_t hbm_class[kNumD];   // in-LDS class sorting HBM chunks of width D (-1: tiles)
+    int32_t plain_tile_keys[kNumD];   // plain form: tiles of sub-arrays merged through HBM
     int64_t lb_cap;
     int32_t flags;
 };
@@ -276,8 +302,13 @@ hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_class(const Job* J, const Bounds& b, int D, int c, hipStream_t s);
-hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s);
-hipError_t launch_merge_phase(const Job* J, const Bounds& b, int phase, hipStream_t s);
+// sub-arrays merged through HBM: chunk sorts in LDS, then `phases` merge-split
+// phases (phases < 0: the host bound b.phase_bound)
+hipError_t launch_merges(const Job* J, const Bounds& b, int phases, hipStream_t s);
+hipError_t launch_hbm_chunks(const Job* J, const Bounds& b, int D, hipStream_t s);
+hipError_t launch_merge_pairs(const Job* J, const Bounds& b, int phase, hipStream_t s);
+// dynamic LDS the batched pair merge needs for records up to dmax dwords
+int pair_merge_lds(int dmax);
 // plain per-bucket form pieces
 hipError_t launch_pack(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_tile_one_bucket(const Job* J, int D, const TileDesc& first, int ntiles,

@@ -16,6 +16,8 @@
 // K per tile is the smallest power of two >= ceil(n/64) (at least 2), up to a
 // bound that keeps D*K <= 128 record VGPRs, so small sub-arrays do not pay
 // for the full tile width.
+#include <algorithm>
+
 #include "bsort_internal.h"
 
 namespace bsort {
@@ -504,29 +506,38 @@ __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, in
 }
 
 template <int D, int NT, int CAP>
-__global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, int cls) {
+__global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, int list) {
     __shared__ uint32_t lds[D * CAP];
     constexpr int NW = NT / kWave;
     constexpr int Dk = D - 1, W = (Dk + 1) / 2;
     constexpr int KCAP = kmax_for(D) < kLdsMaxTile / kWave ? kmax_for(D) : kLdsMaxTile / kWave;
     static_assert(D * CAP * 4 <= kLdsBytes, "sub-array does not fit the LDS budget");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int slot = D * kLdsClasses + cls;
-    int64_t cnt = J->lb_count[slot];
-    if (cnt > J->lb_cap) cnt = J->lb_cap;
-    const LBucket* list = J->lbuckets + slot * J->lb_cap;
+    // list < kLdsClasses: the sub-arrays of that size class; list ==
+    // kLdsClasses: chunks of sub-arrays that are merged through HBM next
+    int64_t cnt;
+    const LBucket* lst;
+    if (list < kLdsClasses) {
+        const int slot = D * kLdsClasses + list;
+        cnt = J->lb_count[slot] < J->lb_cap ? J->lb_count[slot] : J->lb_cap;
+        lst = J->lbuckets + slot * J->lb_cap;
+    } else {
+        cnt = J->hc_count[D] < J->tile_cap[D] ? J->hc_count[D] : J->tile_cap[D];
+        lst = J->hchunks[D];
+    }
     const bool tiles_only = (J->flags & kFlagTilesOnly) != 0;
     const int T = tiles_only ? J->tile_keys[D] : lds_tile(J->tile_keys[D], CAP, D);
     const int logT = 31 - __builtin_clz(T);               // tile sizes are powers of two
     for (int64_t bi = blockIdx.x; bi < cnt; bi += gridDim.x) {
-        const LBucket bk = list[bi];
-        const int n = bk.n_b;                          // T < n <= CAP (checked when listed)
-        const uint64_t* keys = J->keys + bk.key_off;
+        const LBucket bk = lst[bi];
+        const int n = bk.n_b;                          // n <= CAP (checked when listed)
+        const int64_t ks = bk.stride;                  // key lane stride
+        uint64_t* keys = J->keys + bk.key_off;
         int32_t* perm = J->perm + bk.pos0;
         for (int i = tid; i < n; i += NT) {
 #pragma unroll
             for (int w = 0; w < W; ++w) {
-                const uint64_t v = keys[(int64_t)w * n + i];
+                const uint64_t v = keys[w * ks + i];
                 lds[(2 * w) * CAP + i] = (uint32_t)(v >> 32);
                 if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + i] = (uint32_t)v;
             }
@@ -544,7 +555,17 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         if (!tiles_only)
             for (int s = 0; s < p; ++s)
                 lds_merge_phase<D, NT, CAP>(lds, n, T, logT, p, s, tid);
-        for (int i = tid; i < n; i += NT) perm[i] = (int32_t)lds[Dk * CAP + i];
+        for (int i = tid; i < n; i += NT) {
+            perm[i] = (int32_t)lds[Dk * CAP + i];
+            if (bk.wk) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const uint64_t hi = lds[(2 * w) * CAP + i];
+                    const uint64_t lo = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP + i] : 0u;
+                    keys[w * ks + i] = (hi << 32) | lo;
+                }
+            }
+        }
         __syncthreads();                               // LDS reused by the next sub-array
     }
 }
@@ -581,15 +602,15 @@ static const BucketLauncher kBucketLaunchers[kNumD] = {
     launch_bucket_d<17>};
 
 template <int D, int C>
-static void launch_lds_class_t(const Job* J, int64_t lb_cap, hipStream_t s) {
+static void launch_lds_class_t(const Job* J, int64_t grid, int list, hipStream_t s) {
     if constexpr (lds_fits(D, C)) {
-        int64_t g = lb_cap < 1024 ? lb_cap : 1024;
+        int64_t g = grid < 1024 ? grid : 1024;
         if (g < 1) g = 1;
-        k_bucket_lds<D, lds_threads(C, D), lds_cap(C, D)><<<(unsigned)g, lds_threads(C, D), 0, s>>>(J, C);
+        k_bucket_lds<D, lds_threads(C, D), lds_cap(C, D)><<<(unsigned)g, lds_threads(C, D), 0, s>>>(J, list);
     }
 }
 
-using LdsLauncher = void (*)(const Job*, int64_t, hipStream_t);
+using LdsLauncher = void (*)(const Job*, int64_t, int, hipStream_t);
 #define BSORT_LDS_ROW(D) \
     {launch_lds_class_t<D, 0>, launch_lds_class_t<D, 1>, launch_lds_class_t<D, 2>, \
      launch_lds_class_t<D, 3>, launch_lds_class_t<D, 4>}
@@ -600,7 +621,7 @@ static const LdsLauncher kLdsLaunchers[kLdsMaxD + 1][kLdsClasses] = {
 hipError_t launch_lds_class(const Job* J, const Bounds& b, int D, int c, hipStream_t s) {
     if (D < 2 || D > kLdsMaxD || c < 0 || c >= kLdsClasses) return hipErrorInvalidValue;
     if (!lds_fits(D, c)) return hipSuccess;
-    kLdsLaunchers[D][c](J, b.lb_cap, s);
+    kLdsLaunchers[D][c](J, b.lb_cap, c, s);
     return hipGetLastError();
 }
 
@@ -610,6 +631,137 @@ hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t 
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// chunks of sub-arrays merged through HBM, sorted by the in-LDS kernel of
+// class b.hbm_class[D] (keys written back for the merges)
+hipError_t launch_hbm_chunks(const Job* J, const Bounds& b, int D, hipStream_t s) {
+    if (D < 2 || D > kLdsMaxD) return hipErrorInvalidValue;
+    const int c = b.hbm_class[D];
+    if (c < 0 || !lds_fits(D, c)) return hipSuccess;
+    kLdsLaunchers[D][c](J, b.tile_cap, kLdsClasses, s);
+    return hipGetLastError();
+}
+
+// ---- merge-split through HBM, one tile pair per workgroup
+
+// records a pair merge of width D holds in LDS: two tiles of the HBM tile
+// size (chunk size for in-LDS widths, a register tile's size otherwise)
+__host__ __device__ constexpr int pair_cap(int D) {
+    return 2 * (D <= kLdsMaxD ? hbm_chunk_max(D) : kWave * kmax_for(D));
+}
+constexpr int kPairThreads = 512;
+
+// Tiles m.a and m.a+1 of one sub-array (both sorted) merged in LDS and
+// written back in place, the lower tile receiving the smaller half: one
+// phase of the in-LDS merge-split over a two-tile array.
+template <int D>
+__device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, uint32_t* lds,
+                               int* sflag, int tid) {
+    constexpr int CAP2 = pair_cap(D);
+    constexpr int Dk = D - 1, W = (Dk + 1) / 2;
+    const int T = m.T;                                 // power of two, 2T <= CAP2
+    const int logT = 31 - __builtin_clz(T);
+    const int64_t lo = (int64_t)m.a * T;
+    const int rest = m.n_b - (m.a + 1) * T;
+    const int nb = rest < T ? rest : T;
+    const int tot = T + nb;
+    const int64_t ks = m.n_b;
+    uint64_t* keys = J->keys + m.key_off + lo;
+    int32_t* perm = J->perm + m.pos0 + lo;
+    if (tid == 0) {                                    // in order across the seam: no moves
+        int gt = 0;
+        for (int w = 0; w < W; ++w) {
+            const uint64_t x = keys[w * ks + T - 1], y = keys[w * ks + T];
+            if (x != y) {
+                gt = x > y;
+                break;
+            }
+        }
+        *sflag = gt;
+    }
+    __syncthreads();
+    if (*sflag == 0) return;                           // uniform
+    for (int i = tid; i < tot; i += kPairThreads) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t v = keys[w * ks + i];
+            lds[(2 * w) * CAP2 + i] = (uint32_t)(v >> 32);
+            if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP2 + i] = (uint32_t)v;
+        }
+        lds[Dk * CAP2 + i] = (uint32_t)perm[i];
+    }
+    __syncthreads();
+    lds_merge_phase<D, kPairThreads, CAP2>(lds, tot, T, logT, 2, 0, tid);
+    for (int i = tid; i < tot; i += kPairThreads) {
+        perm[i] = (int32_t)lds[Dk * CAP2 + i];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t hi = lds[(2 * w) * CAP2 + i];
+            const uint64_t lo32 = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP2 + i] : 0u;
+            keys[w * ks + i] = (hi << 32) | lo32;
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void merge_pair_d(const Job* J, const MergeItem& m, uint32_t* lds,
+                                             int* sflag, int tid, int d) {
+    if constexpr (D <= kMaxD) {
+        if (d == D) merge_pair_lds<D>(J, m, lds, sflag, tid);
+        else merge_pair_d<D + 1>(J, m, lds, sflag, tid, d);
+    }
+}
+
+// phase s: every queued tile pair of every sub-array merged through HBM; each
+// pair queues its successors of phase s+1
+__global__ __launch_bounds__(kPairThreads) void k_merge_pairs(const Job* __restrict__ J, int s) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int sflag;
+    if (s >= J->phase_cap) return;
+    int cnt = J->mcount[s];
+    if (cnt > J->merge_cap) cnt = (int)J->merge_cap;
+    const MergeItem* items = J->mlist[s & 1];
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+        const MergeItem m = items[it];
+        merge_pair_d<2>(J, m, lds, &sflag, tid, dwords_for_len(m.L));
+        if (tid == 0 && s + 1 < m.p) {
+            // successors: pair (a+1, a+2); after an odd phase also (0, 1)
+            if (m.a + 2 < m.p) {
+                MergeItem n = m;
+                n.a = m.a + 1;
+                n.s = s + 1;
+                push_item(J, s + 1, n);
+            }
+            if ((s & 1) && m.a == 1) {
+                MergeItem n = m;
+                n.a = 0;
+                n.s = s + 1;
+                push_item(J, s + 1, n);
+            }
+        }
+        __syncthreads();                               // LDS and sflag reused by the next item
+    }
+}
+
+int pair_merge_lds(int dmax) {
+    int need = 0;
+    for (int D = 2; D <= dmax && D <= kMaxD; ++D) need = std::max(need, pair_cap(D) * 4 * D);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_merge_pairs,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        attr = true;
+    }
+    return need;
+}
+
+hipError_t launch_merge_pairs(const Job* J, const Bounds& b, int phase, hipStream_t s) {
+    const int64_t cap = (b.total / kMinTile + (int64_t)b.R * b.ml1) / 2 + 1;
+    const int64_t g = cap < 1024 ? cap : 1024;
+    k_merge_pairs<<<(unsigned)(g < 1 ? 1 : g), kPairThreads, b.pair_lds, s>>>(J, phase);
+    return hipGetLastError();
 }
 
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s) {

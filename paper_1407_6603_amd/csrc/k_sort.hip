@@ -9,12 +9,11 @@
 //   k_pack        one wave per 1,024-word chunk: big-endian uint64 key lanes
 //                 (the paper's fixed-width word slots, Section III approach
 //                 two) and the initial index payload
-//   k_merge_phase one workgroup per (sub-array, tile pair) of one phase of
-//                 the block odd-even merge-split (Baudet and Stevenson,
-//                 1978): tiles a and a+1 of a sub-array, both sorted, are
-//                 merged; the lower keeps the smaller half.  p phases sort a
-//                 sub-array of p tiles.  Each item queues its successors of
-//                 the next phase.
+//   k_merge_bucket the plain per-bucket form's merge-split of one sub-array's
+//                 tile pairs of one phase (Baudet and Stevenson, 1978): tiles
+//                 a and a+1, both sorted, are merged in LDS; the lower keeps
+//                 the smaller half.  (The batched form's pair merge is
+//                 k_merge_pairs, with the in-LDS kernels.)
 #include "bsort_internal.h"
 
 namespace bsort {
@@ -24,6 +23,8 @@ __global__ __launch_bounds__(256) void k_sort_init(const Job* __restrict__ J) {
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     if (i0 < kNumD) J->tile_count[i0] = 0;
     if (i0 < kNumD * kLdsClasses) J->lb_count[i0] = 0;
+    if (i0 <= kLdsMaxD) J->hc_count[i0] = 0;
+    if (i0 == 0) J->pmax[0] = 0;
     for (int64_t i = i0; i <= J->phase_cap; i += step) J->mcount[i] = 0;
 }
 
@@ -37,9 +38,12 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     __shared__ int64_t blk_item_base;
     __shared__ int blk_lb[kNumD * kLdsClasses];
     __shared__ int64_t blk_lb_base[kNumD * kLdsClasses];
+    __shared__ int blk_hc[kLdsMaxD + 1];
+    __shared__ int64_t blk_hc_base[kLdsMaxD + 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid < kNumD) blk_tiles[tid] = 0;
     if (tid < kNumD * kLdsClasses) blk_lb[tid] = 0;
+    if (tid <= kLdsMaxD) blk_hc[tid] = 0;
     if (tid == 0) blk_items = 0;
     __syncthreads();
 
@@ -91,11 +95,17 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
                 lcls[k] = c;
                 tslot[k] = atomicAdd(&blk_lb[D * kLdsClasses + c], 1);
             } else {
+                // merged through HBM: chunks sorted in LDS (D <= kLdsMaxD) or
+                // register tiles, then nt merge-split phases
                 route[k] = 3;
                 const int T = J->hbm_tile_keys[D];
                 nt[k] = (nb + T - 1) / T;
-                tslot[k] = atomicAdd(&blk_tiles[D], nt[k]);
-                if (nt[k] >= 2 && !tiles_only) islot[k] = atomicAdd(&blk_items, nt[k] / 2);
+                if (D <= kLdsMaxD) tslot[k] = atomicAdd(&blk_hc[D], nt[k]);
+                else tslot[k] = atomicAdd(&blk_tiles[D], nt[k]);
+                if (nt[k] >= 2 && !tiles_only) {
+                    islot[k] = atomicAdd(&blk_items, nt[k] / 2);
+                    atomicMax(J->pmax, nt[k]);
+                }
             }
         }
     }
@@ -105,6 +115,8 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     if (tid == kNumD && blk_items > 0) blk_item_base = atomicAdd(&J->mcount[0], blk_items);
     if (tid < kNumD * kLdsClasses && blk_lb[tid] > 0)
         blk_lb_base[tid] = atomicAdd(&J->lb_count[tid], blk_lb[tid]);
+    if (tid <= kLdsMaxD && blk_hc[tid] > 0)
+        blk_hc_base[tid] = atomicAdd(&J->hc_count[tid], blk_hc[tid]);
     __syncthreads();
     if (!active) return;
 
@@ -127,16 +139,30 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
             lb.key_off = ko;
             lb.n_b = nb;
             lb.L = L;
+            lb.stride = nb;
+            lb.wk = 0;
             J->lbuckets[sl * J->lb_cap + at] = lb;
             continue;
         }
         const int T = route[k] == 1 ? nb : J->hbm_tile_keys[D];
-        const int64_t base = blk_tile_base[D] + tslot[k];
+        const bool chunks = route[k] == 3 && D <= kLdsMaxD;
+        const int64_t base = (chunks ? blk_hc_base[D] : blk_tile_base[D]) + tslot[k];
         if (base + nt[k] > J->tile_cap[D]) {
             set_status(J, ST_OVERFLOW);
             continue;
         }
-        for (int t = 0; t < nt[k]; ++t) {
+        if (chunks) {
+            for (int t = 0; t < nt[k]; ++t) {
+                LBucket lb;
+                lb.pos0 = pos0 + (int64_t)t * T;
+                lb.key_off = ko + (int64_t)t * T;
+                lb.n_b = nb - t * T < T ? nb - t * T : T;
+                lb.L = L;
+                lb.stride = nb;
+                lb.wk = 1;
+                J->hchunks[D][base + t] = lb;
+            }
+        } else for (int t = 0; t < nt[k]; ++t) {
             TileDesc d;
             d.pos0 = pos0;
             d.key_off = ko;
@@ -355,41 +381,6 @@ __device__ void merge_pair(const Job* __restrict__ J, const MergeItem& m, bool l
     }
 }
 
-__device__ __forceinline__ void push_item(const Job* J, int s1, const MergeItem& m) {
-    const int slot = atomicAdd(&J->mcount[s1], 1);
-    if (slot < J->merge_cap) J->mlist[s1 & 1][slot] = m;
-    else set_status(J, ST_OVERFLOW);
-}
-
-__global__ __launch_bounds__(1024) void k_merge_phase(const Job* __restrict__ J, int s,
-                                                      int lds_dwords) {
-    extern __shared__ uint32_t lds[];
-    __shared__ int sflag;
-    if (s >= J->phase_cap) return;
-    int cnt = J->mcount[s];
-    if (cnt > J->merge_cap) cnt = (int)J->merge_cap;
-    const MergeItem* list = J->mlist[s & 1];
-    for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
-        const MergeItem m = list[it];
-        merge_pair(J, m, s == m.p - 1, lds, lds_dwords, &sflag);
-        if (threadIdx.x == 0 && s + 1 < m.p) {
-            // successors: pair (a+1, a+2); after an odd phase also (0, 1)
-            if (m.a + 2 < m.p) {
-                MergeItem n = m;
-                n.a = m.a + 1;
-                n.s = s + 1;
-                push_item(J, s + 1, n);
-            }
-            if ((s & 1) && m.a == 1) {
-                MergeItem n = m;
-                n.a = 0;
-                n.s = s + 1;
-                push_item(J, s + 1, n);
-            }
-        }
-        __syncthreads();                            // LDS and sflag reused by the next item
-    }
-}
 
 // plain form: one launch per (sub-array, phase); block x takes pair a = (s&1) + 2x
 __global__ __launch_bounds__(1024) void k_merge_bucket(const Job* __restrict__ J, MergeItem m,
@@ -419,8 +410,6 @@ int merge_lds_budget() {
         v -= 1024;                                   // room for the static __shared__ words
         if (v > 160 * 1024) v = 160 * 1024;
         budget = v;
-        (void)hipFuncSetAttribute((const void*)k_merge_phase,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, budget);
         (void)hipFuncSetAttribute((const void*)k_merge_bucket,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, budget);
     }
@@ -429,13 +418,6 @@ int merge_lds_budget() {
 
 hipError_t launch_pack(const Job* J, const Bounds& b, hipStream_t s) {
     k_pack<<<grid_for2(b.chunk_cap, kTileWavesPerBlock, 0x7fffffff), 256, 0, s>>>(J);
-    return hipGetLastError();
-}
-
-hipError_t launch_merge_phase(const Job* J, const Bounds& b, int phase, hipStream_t s) {
-    const int64_t merge_cap = (b.total / kMinTile + (int64_t)b.R * b.ml1) / 2 + 1;
-    k_merge_phase<<<grid_for2(merge_cap, 1, 4096), b.merge_threads, b.merge_lds, s>>>(
-        J, phase, b.merge_lds / 4);
     return hipGetLastError();
 }
 
@@ -454,10 +436,16 @@ hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s) {
     return launch_pack(J, b, s);
 }
 
-hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s) {
+hipError_t launch_merges(const Job* J, const Bounds& b, int phases, hipStream_t s) {
+    for (int D = 2; D <= b.dmax && D <= kLdsMaxD; ++D) {
+        if (b.hbm_class[D] < 0) continue;
+        hipError_t e = launch_hbm_chunks(J, b, D, s);
+        if (e != hipSuccess) return e;
+    }
     if (b.flags & kFlagTilesOnly) return hipSuccess;
-    for (int ph = 0; ph < b.phase_bound; ++ph) {
-        hipError_t e = launch_merge_phase(J, b, ph, s);
+    if (phases < 0 || phases > b.phase_bound) phases = b.phase_bound;
+    for (int ph = 0; ph < phases; ++ph) {
+        hipError_t e = launch_merge_pairs(J, b, ph, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

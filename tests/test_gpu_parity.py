@@ -288,6 +288,19 @@ def test_zero_one_lds_classes(bs, ws, L):
     assert np.array_equal(got, zero_one_expect(seqs))
 
 
+def test_large_serve_request_merged_through_hbm(bs, ws):
+    """A 1,000,000-word request of the serving workload (lengths to 32, one
+    200,000-word vocabulary): its large sub-arrays are cut into chunks sorted
+    in LDS and merged phase by phase through HBM."""
+    w = wordgen.serve_request(3, 1_000_000)
+    expect = oracle.definition_sort(w.bytes, w.offsets)
+    assert np.array_equal(gpu_sort(bs, ws, w, 32), expect)
+    # the same through a two-list batch (phase count read back per call)
+    batch = wordgen.Batch.concat([w, wordgen.serve_request(4, 3000)])
+    got = gpu_batch(bs, ws, batch, 32)
+    assert np.array_equal(got[:w.n], expect)
+
+
 # ------------------------------------------------------------- batches
 
 @pytest.fixture(scope="module")
