@@ -152,8 +152,9 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
                               void *ws, size_t ws_bytes, bsort_stream_t stream);
 
 /*
- * Stage timing.  A batch sort has these stages: "bucketize", "pack" (tile
- * planning and key packing), one "tiles_d<D>" tile-sort launch per record
+ * Stage timing.  A batch sort has these stages: "bucketize" (in a batch sort
+ * the scatter by length also packs each word's key lanes in place), "pack"
+ * (tile planning), one "tiles_d<D>" tile-sort launch per record
  * width D = 2 .. ceil(max_len/4)+1 (D = ceil(L/4)+1 for words of L bytes),
  * one "lds_d<D>_<C>" launch per in-LDS size class of capacity C words for
  * D = 2 .. min(5, ceil(max_len/4)+1) (sub-arrays sorted whole in LDS; C =

@@ -351,6 +351,7 @@ static Job batch_job(const Layout& L, char* ws, const Bounds& bd, const bsort_ba
     j.starts = (int32_t*)(ws + L.starts);
     j.order = (int32_t*)(ws + L.order);
     j.perm = perm;
+    if (bd.fused_pack) j.flags |= kJobFusedPack;
     return j;
 }
 
@@ -600,6 +601,7 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
     if (t && (t->flags & BSORT_FLAG_PER_BUCKET_LAUNCH))
         return plain_form(b, perm, t, L, (char*)ws, s);
     Bounds bd = make_bounds(L, total, b->n_requests, n_max, t);
+    bd.fused_pack = 1;                                 // bucketize runs in this call
     Job* jd = (Job*)((char*)ws + L.job);
     Job j = batch_job(L, (char*)ws, bd, b, total, perm);
     HIP_TRY(launch_set_job(j, jd, s));
@@ -642,6 +644,7 @@ bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap
     if (t) p->tun = *t;
     make_layout(cap_words, cap_requests, max_len, p->lay);
     p->bd = make_bounds(p->lay, cap_words, cap_requests, p->cap_req, t);
+    p->bd.fused_pack = 1;
     p->job_dev = nullptr;
     p->exec = nullptr;
     hipStream_t cs = nullptr;

@@ -33,7 +33,10 @@ constexpr int kChunk = kWave * kChunkRounds;   // words per bucketize chunk
 constexpr int kTileWavesPerBlock = 4;
 constexpr int kMinTile = 128;             // 64 lanes x 2 records
 constexpr int kFlagTilesOnly = 2;         // same value as BSORT_FLAG_TILES_ONLY
-constexpr int kJobKeepStatus = 1 << 8;    // Job.flags: leave the status word as it is
+constexpr int kJobKeepStatus = 1 << 8;
+// Job.flags: the scatter by length also packs each word's key lanes and index
+// payload at its place in the sub-array (batched form; order is not written)
+constexpr int kJobFusedPack = 1 << 9;    // Job.flags: leave the status word as it is
 constexpr int kMergeGrid = 1024;          // workgroups of the persistent merge kernel
 constexpr int kMaxPhaseCap = 1 << 22;
 
@@ -263,6 +266,46 @@ __device__ __forceinline__ void cex(uint32_t (&a)[D], uint32_t (&b)[D]) {
     }
 }
 
+// W = ceil(L/8) big-endian uint64 lanes of the L bytes at p; bytes past L are
+// zero.  Aligned dword loads when the covering dwords lie inside [lo, hi);
+// single bytes otherwise.
+__device__ __forceinline__ void pack_word(const uint8_t* lo, const uint8_t* hi, const uint8_t* p,
+                                          int L, uint64_t* __restrict__ out, int64_t stride) {
+    const int W = lanes_for_len(L);
+    const uintptr_t addr = (uintptr_t)p;
+    const uintptr_t a4 = addr & ~(uintptr_t)3;
+    const int sh = (int)(addr & 3);
+    const int nd = (sh + L + 3) >> 2;                // dwords covering the word
+    if (a4 >= (uintptr_t)lo && a4 + 4 * (uintptr_t)nd <= (uintptr_t)hi) {
+        const uint32_t* q = (const uint32_t*)a4;
+        uint32_t prev = q[0];
+        uint64_t acc = 0;
+        const int dk = (L + 3) >> 2;                 // key dwords
+        for (int i = 0; i < dk; ++i) {
+            const uint32_t next = i + 1 < nd ? q[i + 1] : 0u;
+            const uint32_t raw = __builtin_amdgcn_alignbyte(next, prev, sh);   // bytes 4i..4i+3
+            prev = next;
+            uint32_t be = __builtin_bswap32(raw);
+            const int valid = L - 4 * i;
+            if (valid < 4) be &= 0xFFFFFFFFu << (8 * (4 - valid));
+            if ((i & 1) == 0) {
+                acc = (uint64_t)be << 32;
+            } else {
+                acc |= be;
+                out[(int64_t)(i >> 1) * stride] = acc;
+            }
+        }
+        if (dk & 1) out[(int64_t)(dk >> 1) * stride] = acc;
+    } else {
+        for (int w = 0; w < W; ++w) {
+            uint64_t v = 0;
+            const int k1 = L - 8 * w < 8 ? L - 8 * w : 8;
+            for (int k = 0; k < k1; ++k) v |= (uint64_t)p[8 * w + k] << (56 - 8 * k);
+            out[(int64_t)w * stride] = v;
+        }
+    }
+}
+
 // queue a merge item for phase s1
 __device__ __forceinline__ void push_item(const Job* J, int s1, const MergeItem& m) {
     if (s1 >= J->phase_cap) {
@@ -291,6 +334,7 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
     int32_t hbm_tile_keys[kNumD];
     int32_t hbm_class[kNumD];   // in-LDS class sorting HBM chunks of width D (-1: tiles)
     int32_t plain_tile_keys[kNumD];   // plain form: tiles of sub-arrays merged through HBM
+    int32_t fused_pack;      // the scatter packs keys (kJobFusedPack); no k_pack launch
     int64_t lb_cap;
     int32_t flags;
 };

@@ -115,36 +115,67 @@ __global__ __launch_bounds__(256) void k_chunk_scan(const Job* __restrict__ J) {
     if (lane == 0) J->counts[(int64_t)r * ml1 + L] = run;
 }
 
+// starts = exclusive scan of counts; key_off = each sub-array's first key
+// lane: wmax lanes per word of the list before it, then ceil(L/8) lanes per
+// word of the shorter sub-arrays (the same layout the tile plan checks)
 __global__ __launch_bounds__(256) void k_bucket_starts(const Job* __restrict__ J) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ml1 = J->ml1;
     const int r = blockIdx.x * kTileWavesPerBlock + wv;
     if (r >= J->R) return;
+    int64_t a, b;
+    req_bounds(J, r, a, b);
     const int32_t* cnt = J->counts + (int64_t)r * ml1;
     int32_t* st = J->starts + (int64_t)r * (ml1 + 1);
+    int64_t* ko = J->key_off + (int64_t)r * ml1;
     int run = 0;
+    int64_t krun = (int64_t)lanes_for_len(J->max_len) * a;
     for (int base = 0; base < ml1; base += kWave) {
         const int L = base + lane;
         const int v = L < ml1 ? cnt[L] : 0;
         const int incl = wave_incl_scan(v, lane);
-        if (L < ml1) st[L] = run + incl - v;
+        const int64_t kv = L < ml1 ? (int64_t)lanes_for_len(L) * v : 0;
+        const int64_t kincl = wave_incl_scan(kv, lane);
+        if (L < ml1) {
+            st[L] = run + incl - v;
+            ko[L] = krun + kincl - kv;
+        }
         run += __shfl(incl, kWave - 1, kWave);
+        krun += __shfl(kincl, kWave - 1, kWave);
     }
     if (lane == 0) st[ml1] = run;
 }
 
+// Stable placement by length: a word's place in its list's sub-array is the
+// sub-array start, the words of that length in earlier chunks, and the
+// earlier lanes of this chunk with the same length.  Writes order, or in the
+// batched form (kJobFusedPack) the word's key lanes and index payload at that
+// place directly.
 __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ J) {
     __shared__ int run[kTileWavesPerBlock][kMaxLen + 1];
+    __shared__ int nbs[kTileWavesPerBlock][kMaxLen + 1];
+    __shared__ int64_t kos[kTileWavesPerBlock][kMaxLen + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t c = (int64_t)blockIdx.x * kTileWavesPerBlock + wv;
     int r;
     int64_t a, b, gs, ge;
     if (!chunk_range(J, c, r, a, b, gs, ge)) return;
     const int ml1 = J->ml1;
+    const bool fused = (J->flags & kJobFusedPack) != 0;
     const int32_t* st = J->starts + (int64_t)r * (ml1 + 1);
-    for (int L = lane; L < ml1; L += kWave) run[wv][L] = st[L] + J->chunk_hist[c * ml1 + L];
+    for (int L = lane; L < ml1; L += kWave) {
+        run[wv][L] = st[L] + J->chunk_hist[c * ml1 + L];
+        if (fused) {
+            nbs[wv][L] = J->counts[(int64_t)r * ml1 + L];
+            kos[wv][L] = J->key_off[(int64_t)r * ml1 + L];
+        }
+    }
     __builtin_amdgcn_wave_barrier();
     const int64_t nr = b - a;
+    const int wmax = lanes_for_len(J->max_len);
+    const int64_t first = J->offsets[0];             // nothing below it is read
+    const uint8_t* blo = J->bytes + (first > 0 ? first : 0);
+    const uint8_t* bhi = J->bytes + J->n_bytes;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     for (int i = 0; i < kChunkRounds; ++i) {
         const int64_t g = gs + (int64_t)i * kWave + lane;
@@ -164,8 +195,22 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ J) {
             const int rank = __popcll(m & lt);          // earlier lanes, same length
             const int base = run[wv][L];
             const int64_t pos = (int64_t)base + rank;
-            if (pos >= 0 && pos < nr) J->order[a + pos] = (int32_t)(g - a);
-            else set_status(J, ST_OVERFLOW);
+            if (pos < 0 || pos >= nr) {
+                set_status(J, ST_OVERFLOW);
+            } else if (!fused) {
+                J->order[a + pos] = (int32_t)(g - a);
+            } else {
+                const int64_t j = pos - st[L];           // place inside the sub-array
+                const int nb = nbs[wv][L];
+                const int64_t ko = kos[wv][L];
+                if (j < 0 || j >= nb || ko < (int64_t)wmax * a ||
+                    ko + (int64_t)lanes_for_len(L) * nb > (int64_t)wmax * b) {
+                    set_status(J, ST_BAD_REQ);
+                } else {
+                    if (L > 0) pack_word(blo, bhi, J->bytes + J->offsets[g], L, J->keys + ko + j, nb);
+                    J->perm[a + pos] = (int32_t)(g - a);
+                }
+            }
             __builtin_amdgcn_wave_barrier();
             if (rank == 0) run[wv][L] = base + __popcll(m);
         }

@@ -195,46 +195,6 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     }
 }
 
-// W = ceil(L/8) big-endian uint64 lanes of the L bytes at p; bytes past L are
-// zero.  Aligned dword loads when the covering dwords lie inside [lo, hi);
-// single bytes otherwise.
-__device__ __forceinline__ void pack_word(const uint8_t* lo, const uint8_t* hi, const uint8_t* p,
-                                          int L, uint64_t* __restrict__ out, int64_t stride) {
-    const int W = lanes_for_len(L);
-    const uintptr_t addr = (uintptr_t)p;
-    const uintptr_t a4 = addr & ~(uintptr_t)3;
-    const int sh = (int)(addr & 3);
-    const int nd = (sh + L + 3) >> 2;                // dwords covering the word
-    if (a4 >= (uintptr_t)lo && a4 + 4 * (uintptr_t)nd <= (uintptr_t)hi) {
-        const uint32_t* q = (const uint32_t*)a4;
-        uint32_t prev = q[0];
-        uint64_t acc = 0;
-        const int dk = (L + 3) >> 2;                 // key dwords
-        for (int i = 0; i < dk; ++i) {
-            const uint32_t next = i + 1 < nd ? q[i + 1] : 0u;
-            const uint32_t raw = __builtin_amdgcn_alignbyte(next, prev, sh);   // bytes 4i..4i+3
-            prev = next;
-            uint32_t be = __builtin_bswap32(raw);
-            const int valid = L - 4 * i;
-            if (valid < 4) be &= 0xFFFFFFFFu << (8 * (4 - valid));
-            if ((i & 1) == 0) {
-                acc = (uint64_t)be << 32;
-            } else {
-                acc |= be;
-                out[(int64_t)(i >> 1) * stride] = acc;
-            }
-        }
-        if (dk & 1) out[(int64_t)(dk >> 1) * stride] = acc;
-    } else {
-        for (int w = 0; w < W; ++w) {
-            uint64_t v = 0;
-            const int k1 = L - 8 * w < 8 ? L - 8 * w : 8;
-            for (int k = 0; k < k1; ++k) v |= (uint64_t)p[8 * w + k] << (56 - 8 * k);
-            out[(int64_t)w * stride] = v;
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ J) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t c = (int64_t)blockIdx.x * kTileWavesPerBlock + wv;
@@ -429,11 +389,14 @@ hipError_t launch_merge_one_bucket(const Job* J, const MergeItem& item0, int npa
 }
 
 hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s) {
-    hipError_t e = launch_chunk_plan(J, false, s);       // k_pack's chunk map
-    if (e != hipSuccess) return e;
+    if (!b.fused_pack) {
+        hipError_t e = launch_chunk_plan(J, false, s);   // k_pack's chunk map
+        if (e != hipSuccess) return e;
+    }
     k_sort_init<<<grid_for2((int64_t)b.phase_bound + kNumD + 1, 256, 1024), 256, 0, s>>>(J);
     k_tile_plan<<<grid_for2(b.R, kTileWavesPerBlock, 0x7fffffff), 256, 0, s>>>(J);
-    return launch_pack(J, b, s);
+    // keys already written by the scatter when it packs (batched form)
+    return b.fused_pack ? hipGetLastError() : launch_pack(J, b, s);
 }
 
 hipError_t launch_merges(const Job* J, const Bounds& b, int phases, hipStream_t s) {
