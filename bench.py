@@ -201,7 +201,10 @@ def serve_run(sw, args):
     reqs = [serve.Request(i, float(sw.arrivals[i]), int(b.req_start[i]), int(b.req_start[i + 1]),
                           int(b.offsets[b.req_start[i + 1]] - b.offsets[b.req_start[i]]))
             for i in range(b.R)]
-    ex = serve.GpuExecutor(staging, streams=3)
+    from paper_1407_6603_amd import autotune
+    tile, hbm, src = autotune.lookup(torch.cuda.get_device_name(0), "large4x1M",
+                                     args.tune_cache or autotune.CACHE)
+    ex = serve.GpuExecutor(staging, streams=3, tune=bs_tuning(tile, hbm))
     # warm-up: first launches on each stream (library load, allocator)
     warm = [serve.Request(r.rid, 0.0, r.first_word, r.last_word, r.n_bytes) for r in reqs[:20]]
     serve.Server(ex, pool_bytes=16 << 30).run(warm, keep_perms=False)
@@ -210,6 +213,7 @@ def serve_run(sw, args):
     res = srv.run(reqs, keep_perms=True)
     st = serve.latency_stats(res)
     st.update({"batches": srv.batches, "pool_high_bytes": srv.pool_high,
+               "tile_keys": tile, "hbm_tile_keys": hbm or "default", "tuning_source": src,
                "offered_words_per_s": float(b.total / max(sw.arrivals[-1], 1e-9)),
                "workload": SERVE_DESC + (f" (first {b.R} arrivals)" if args.serve_arrivals else "")})
     if not args.no_cpu_baseline:
@@ -223,6 +227,11 @@ def serve_run(sw, args):
                         "words_checked": int(sum(res[r].n for r in pick)), "bit_exact": ok,
                         "oracle": "definition (stable sort by length, bytes, index)"}
     return st
+
+
+def bs_tuning(tile, hbm):
+    import paper_1407_6603_amd as bs
+    return bs.tuning(tile, 0, 0, hbm)
 
 
 def serve_line(sw, args, gen_s):
@@ -258,7 +267,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tile", type=int, default=0, help="tile_keys (0: autotune cache or default)")
-    ap.add_argument("--merge-threads", type=int, default=0)
+    ap.add_argument("--hbm-tile", type=int, default=0,
+                    help="hbm_tile_keys, the merge-split block width through HBM "
+                         "(0: autotune cache or library default)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-bucket launch form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph timing")
@@ -311,15 +322,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    tile, mthreads, tuned_from = args.tile, args.merge_threads, "flags"
-    if tile == 0 and mthreads == 0:
-        tile, mthreads, tuned_from = autotune.lookup(torch.cuda.get_device_name(0), "batch4096",
+    tile, hbm_tile, tuned_from = args.tile, args.hbm_tile, "flags"
+    if tile == 0 and hbm_tile == 0:
+        tile, hbm_tile, tuned_from = autotune.lookup(torch.cuda.get_device_name(0), "batch4096",
                                                      args.tune_cache or autotune.CACHE)
 
     b_t, o_t = bs.to_device(batch.bytes, batch.offsets, dev)
     rs_t = torch.from_numpy(batch.req_start).to(dev)
     perm = torch.empty(total, dtype=torch.int32, device=dev)
-    tune = bs.tuning(tile, mthreads)
+    tune = bs.tuning(tile, 0, 0, hbm_tile)
     stream = torch.cuda.current_stream()
     ws = bs.Workspace(bs.workspace_bytes(total, max_len, batch.R), dev)
     # one set of stage events per timed step, created (and first recorded) now
@@ -381,7 +392,7 @@ def main():
     # ---- the plain form: one launch per (list, length) sub-array and per phase
     plain = None
     if not args.no_plain:
-        ptune = bs.tuning(tile, mthreads, bs.FLAG_PER_BUCKET_LAUNCH)
+        ptune = bs.tuning(tile, 0, bs.FLAG_PER_BUCKET_LAUNCH, hbm_tile)
         pws = bs.Workspace(bs.workspace_bytes(total, max_len, batch.R), dev)
         pperm = torch.empty(total, dtype=torch.int32, device=dev)
         bs.sort_batch(b_t, o_t, rs_t, batch.req_start, max_len, ptune, pws, out=pperm)
@@ -474,7 +485,7 @@ def main():
                                f"{total} words, lengths 1-12, Zipf 1.1 over an 800-word "
                                "vocabulary per list, 5% capitalised",
                    "global_batch": batch.R, "words": total, "max_len": max_len,
-                   "tile_keys": tile or 256, "merge_threads": mthreads or 256,
+                   "tile_keys": tile or 256, "hbm_tile_keys": hbm_tile or "default",
                    "tuning_source": tuned_from, "parallelism": "single GPU"},
         "graph_plan": graph,
         "per_bucket_launch": plain,
