@@ -61,7 +61,9 @@ def measured_traffic(kernel):
 
 
 def lds_threads(cap_index, D):
-    return 256 if cap_index <= 1 else 512 if (cap_index == 2 or D >= 4) else 1024
+    if cap_index <= 1:
+        return 256
+    return 512 if (cap_index <= 3 and D <= 2) or cap_index == 2 or D >= 4 else 1024
 
 
 def kernel_name(stage):

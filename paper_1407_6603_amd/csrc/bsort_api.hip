@@ -38,7 +38,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Workspace layout: a pure function of (total words, lists, max_len), so the
 // size a caller asks for and the layout a call uses always agree.
 struct Layout {
-    size_t status, job, chunk_begin, chunk_hist, key_off, keys, tiles[kNumD], tile_count,
+    size_t status, job, chunk_begin, chunk_list, chunk_hist, key_off, keys, tiles[kNumD], tile_count,
         mlist[2], mcount, counts, starts, order, jobs, lbuckets, lb_count,
         hchunks[kLdsMaxD + 1], hc_count, pmax;
     int64_t chunk_cap, tile_cap, merge_cap, lb_cap;
@@ -66,6 +66,7 @@ bool make_layout(int64_t total, int32_t R, int32_t max_len, Layout& L) {
     L.status = take(256);
     L.job = take(sizeof(Job));
     L.chunk_begin = take(sizeof(int64_t) * ((size_t)R + 1));
+    L.chunk_list = take(sizeof(int32_t) * (size_t)L.chunk_cap);
     L.chunk_hist = take(sizeof(int32_t) * (size_t)L.chunk_cap * L.ml1);
     L.key_off = take(sizeof(int64_t) * (size_t)R * L.ml1);
     L.keys = take(sizeof(uint64_t) * (size_t)L.wmax * (size_t)total);
@@ -171,6 +172,7 @@ Job base_job(const Layout& L, char* ws, const Bounds& b) {
     j.flags = b.flags;
     j.status = (uint32_t*)(ws + L.status);
     j.chunk_begin = (int64_t*)(ws + L.chunk_begin);
+    j.chunk_list = (int32_t*)(ws + L.chunk_list);
     j.chunk_hist = (int32_t*)(ws + L.chunk_hist);
     j.chunk_cap = L.chunk_cap;
     j.key_off = (int64_t*)(ws + L.key_off);
@@ -195,6 +197,7 @@ Job base_job(const Layout& L, char* ws, const Bounds& b) {
     j.merge_cap = L.merge_cap;
     j.mcount = (int32_t*)(ws + L.mcount);
     j.phase_cap = L.phase_cap;
+    j.phase_bound = b.phase_bound;
     return j;
 }
 

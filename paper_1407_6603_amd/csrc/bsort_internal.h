@@ -24,6 +24,18 @@
 
 namespace bsort {
 
+// Views of pointers as global memory.  Pointers read from the job
+// descriptor are generic to the compiler, which then emits flat loads and
+// stores; flat operations also count against the LDS wait counter, so a
+// kernel mixing them with LDS work waits for both at once.  Hot loops read
+// and write through these views instead.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T* p) {
+    return (gptr<T>)p;
+}
+
 constexpr int kMaxLen = 64;
 constexpr int kMaxD = 17;                 // ceil(64/4) + 1
 constexpr int kNumD = kMaxD + 1;          // arrays indexed by D directly
@@ -62,9 +74,11 @@ __host__ __device__ constexpr bool lds_fits(int D, int c) {
     return D >= 2 && D <= kLdsMaxD && D * 4 * lds_cap(c, D) <= kLdsBytes;
 }
 // threads per workgroup: 1024 only where the staged merge outputs still fit
-// the 128 VGPRs a 1024-thread workgroup leaves each lane (D <= 3)
+// the 128 VGPRs a 1024-thread workgroup leaves each lane (D <= 3) and LDS
+// holds one workgroup per CU anyway; 512 for two-dword records up to 8192
+// words, so two workgroups share a CU
 __host__ __device__ constexpr int lds_threads(int c, int D) {
-    return c <= 1 ? 256 : (c == 2 || D >= 4) ? 512 : 1024;
+    return c <= 1 ? 256 : (c <= 3 && D <= 2) || c == 2 || D >= 4 ? 512 : 1024;
 }
 constexpr int kLdsMaxTile = 512;          // tiles inside an LDS sub-array: K <= 8
 // tile size inside an in-LDS sub-array of class capacity cap when the tiles
@@ -156,6 +170,7 @@ struct Job {
     // workspace
     uint32_t* status;            // [1]
     int64_t* chunk_begin;        // [R + 1]
+    int32_t* chunk_list;         // [chunk_cap] list of each chunk (R > 1)
     int32_t* chunk_hist;         // [chunk_cap * ml1], scanned in place
     int64_t chunk_cap;
     int64_t* key_off;            // [R * ml1]
@@ -177,7 +192,7 @@ struct Job {
     int64_t merge_cap;
     int32_t* mcount;             // [phase_cap + 1]
     int32_t phase_cap;
-    int32_t pad0;
+    int32_t phase_bound;         // phases the host launches at most (counters in use)
     int64_t rs_inline[2];        // req_start storage for single-list calls
     int64_t cb_inline[2];        // chunk_begin storage for the plain form's per-list jobs
 };
@@ -185,11 +200,12 @@ struct Job {
 // ---------------------------------------------------------------- helpers
 
 __device__ __forceinline__ void set_status(const Job* J, uint32_t bit) {
-    atomicOr(J->status, bit);
+    __hip_atomic_fetch_or(gp(J->status), bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // largest r in [0, n) with a[r] <= x, for non-decreasing a[0..n] with a[0] <= x
-__device__ __forceinline__ int upper_index(const int64_t* a, int n, int64_t x) {
+template <class P>
+__device__ __forceinline__ int upper_index(P a, int n, int64_t x) {
     int lo = 0, hi = n;        // invariant: a[lo] <= x, answer in [lo, hi)
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
@@ -210,7 +226,8 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
 
 // list r's word range [a, b), clamped into [0, total]
 __device__ __forceinline__ void req_bounds(const Job* J, int r, int64_t& a, int64_t& b) {
-    int64_t x = J->req_start[r], y = J->req_start[r + 1];
+    const gptr<const int64_t> rs = gp(J->req_start);
+    int64_t x = rs[r], y = rs[r + 1];
     x = x < 0 ? 0 : (x > J->total ? J->total : x);
     y = y < x ? x : (y > J->total ? J->total : y);
     a = x;
@@ -222,12 +239,18 @@ __device__ __forceinline__ void req_bounds(const Job* J, int r, int64_t& a, int6
 __device__ __forceinline__ bool chunk_range(const Job* J, int64_t c, int& r, int64_t& a,
                                             int64_t& b, int64_t& gs, int64_t& ge) {
     const int R = J->R;
-    int64_t nch = J->chunk_begin[R];
+    const gptr<const int64_t> cb = gp(J->chunk_begin);
+    int64_t nch = cb[R];
     if (nch > J->chunk_cap) nch = J->chunk_cap;
     if (c >= nch) return false;
-    r = upper_index(J->chunk_begin, R, c);
+    if (R == 1) {
+        r = 0;
+    } else {
+        r = gp(J->chunk_list)[c];
+        if (r < 0 || r >= R) return false;             // table not filled: nothing to do
+    }
     req_bounds(J, r, a, b);
-    gs = a + (c - J->chunk_begin[r]) * kChunk;
+    gs = a + (c - cb[r]) * kChunk;
     ge = gs + kChunk < b ? gs + kChunk : b;
     return true;
 }
@@ -269,15 +292,15 @@ __device__ __forceinline__ void cex(uint32_t (&a)[D], uint32_t (&b)[D]) {
 // W = ceil(L/8) big-endian uint64 lanes of the L bytes at p; bytes past L are
 // zero.  Aligned dword loads when the covering dwords lie inside [lo, hi);
 // single bytes otherwise.
-__device__ __forceinline__ void pack_word(const uint8_t* lo, const uint8_t* hi, const uint8_t* p,
-                                          int L, uint64_t* __restrict__ out, int64_t stride) {
+template <class BP, class OP>
+__device__ __forceinline__ void pack_word(BP lo, BP hi, BP p, int L, OP out, int64_t stride) {
     const int W = lanes_for_len(L);
     const uintptr_t addr = (uintptr_t)p;
     const uintptr_t a4 = addr & ~(uintptr_t)3;
     const int sh = (int)(addr & 3);
     const int nd = (sh + L + 3) >> 2;                // dwords covering the word
     if (a4 >= (uintptr_t)lo && a4 + 4 * (uintptr_t)nd <= (uintptr_t)hi) {
-        const uint32_t* q = (const uint32_t*)a4;
+        const gptr<const uint32_t> q = (gptr<const uint32_t>)a4;
         uint32_t prev = q[0];
         uint64_t acc = 0;
         const int dk = (L + 3) >> 2;                 // key dwords
@@ -341,7 +364,7 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
 
 hipError_t launch_set_job(const Job& j, Job* dst, hipStream_t s);
 hipError_t launch_bucketize(const Job* J, const Bounds& b, hipStream_t s);
-hipError_t launch_chunk_plan(const Job* J, bool clear_status, hipStream_t s);
+hipError_t launch_chunk_plan(const Job* J, const Bounds& b, bool clear_status, hipStream_t s);
 hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s);

@@ -16,20 +16,6 @@
 
 namespace bsort {
 
-// length of global word g, or -1 (with a status bit) if it is malformed
-__device__ __forceinline__ int word_len(const Job* J, int64_t g, uint32_t& bad) {
-    const int64_t o0 = J->offsets[g], o1 = J->offsets[g + 1];
-    if (o0 < 0 || o1 < o0 || o1 > J->n_bytes) {
-        bad |= ST_BAD_OFFSETS;
-        return -1;
-    }
-    if (o1 - o0 > J->max_len) {
-        bad |= ST_TOO_LONG;
-        return -1;
-    }
-    return (int)(o1 - o0);
-}
-
 __global__ void k_set_job(Job j, Job* dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = j;
 }
@@ -71,6 +57,35 @@ __global__ __launch_bounds__(1024) void k_chunk_plan(const Job* __restrict__ J, 
     }
 }
 
+// chunk -> list table: one wave per list writes its chunks' entries
+__global__ __launch_bounds__(256) void k_chunk_lists(const Job* __restrict__ J) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = blockIdx.x * kTileWavesPerBlock + wv;
+    if (r >= J->R) return;
+    const gptr<const int64_t> cb = gp(J->chunk_begin);
+    const int64_t c0 = cb[r];
+    int64_t c1 = cb[r + 1];
+    if (c1 > J->chunk_cap) c1 = J->chunk_cap;
+    const gptr<int32_t> cl = gp(J->chunk_list);
+    for (int64_t c = c0 + lane; c < c1; c += kWave) cl[c] = r;
+}
+
+
+// word length from its two offsets, or -1 (reason in bad) if malformed
+// (outside [first, n_bytes], the readable bytes) or longer than max_len
+__device__ __forceinline__ int word_len_o(int64_t o0, int64_t o1, int64_t first, int64_t n_bytes,
+                                          int max_len, uint32_t& bad) {
+    if (o0 < 0 || o0 < first || o1 < o0 || o1 > n_bytes) {
+        bad |= ST_BAD_OFFSETS;
+        return -1;
+    }
+    if (o1 - o0 > max_len) {
+        bad |= ST_TOO_LONG;
+        return -1;
+    }
+    return (int)(o1 - o0);
+}
+
 __global__ __launch_bounds__(256) void k_chunk_hist(const Job* __restrict__ J) {
     __shared__ int hist[kTileWavesPerBlock][kMaxLen + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -78,20 +93,37 @@ __global__ __launch_bounds__(256) void k_chunk_hist(const Job* __restrict__ J) {
     int r;
     int64_t a, b, gs, ge;
     if (!chunk_range(J, c, r, a, b, gs, ge)) return;     // whole wave; no block barriers below
-    const int ml1 = J->ml1;
+    const int ml1 = J->ml1, max_len = J->max_len;
+    const int64_t n_bytes = J->n_bytes;
+    const gptr<const int64_t> offs = gp(J->offsets);
+    const int64_t first = offs[0];
     for (int L = lane; L < ml1; L += kWave) hist[wv][L] = 0;
     __builtin_amdgcn_wave_barrier();
+    // every word length of the chunk first (independent loads in flight together)
+    // loads at in-range indices (a chunk holds at least one word), no branch
+    // around them, so they are all in flight before the first is used
     uint32_t bad = 0;
+    int64_t oa[kChunkRounds], ob[kChunkRounds];
+#pragma unroll
     for (int i = 0; i < kChunkRounds; ++i) {
         const int64_t g = gs + (int64_t)i * kWave + lane;
-        if (g < ge) {
-            const int L = word_len(J, g, bad);
-            if (L >= 0) atomicAdd(&hist[wv][L], 1);
-        }
+        const int64_t gc = g < ge ? g : ge - 1;
+        oa[i] = offs[gc];
+        ob[i] = offs[gc + 1];
     }
+    int Ls[kChunkRounds];
+#pragma unroll
+    for (int i = 0; i < kChunkRounds; ++i) {
+        const int64_t g = gs + (int64_t)i * kWave + lane;
+        Ls[i] = g < ge ? word_len_o(oa[i], ob[i], first, n_bytes, max_len, bad) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < kChunkRounds; ++i)
+        if (Ls[i] >= 0) atomicAdd(&hist[wv][Ls[i]], 1);
     if (bad) set_status(J, bad);
     __builtin_amdgcn_wave_barrier();
-    for (int L = lane; L < ml1; L += kWave) J->chunk_hist[c * ml1 + L] = hist[wv][L];
+    const gptr<int32_t> ch = gp(J->chunk_hist);
+    for (int L = lane; L < ml1; L += kWave) ch[c * ml1 + L] = hist[wv][L];
 }
 
 __global__ __launch_bounds__(256) void k_chunk_scan(const Job* __restrict__ J) {
@@ -146,13 +178,52 @@ __global__ __launch_bounds__(256) void k_bucket_starts(const Job* __restrict__ J
     if (lane == 0) st[ml1] = run;
 }
 
+// Key lanes of a word of L <= 12 bytes at p: the word lies in the 16 bytes
+// from the dword boundary at or below p, loaded as four dwords (a fixed
+// count, so many words' loads can be in flight together); false if those
+// bytes are not all inside [lo, hi).
+// (the load itself is unconditional: the address is clamped into [lo, hi-16],
+// which the caller guarantees is not empty, and the result only counts when
+// the clamp did not move it)
+__device__ __forceinline__ bool load_short_word(uintptr_t lo, uintptr_t hi, uintptr_t addr,
+                                                uint32_t (&q)[4], int& sh) {
+    const uintptr_t a4 = addr & ~(uintptr_t)3;
+    sh = (int)(addr & 3);
+    const uintptr_t top = (hi - 16) & ~(uintptr_t)3;
+    const uintptr_t lo4 = (lo + 3) & ~(uintptr_t)3;
+    const uintptr_t ac = a4 < lo4 ? lo4 : (a4 > top ? top : a4);
+    const gptr<const uint32_t> w = (gptr<const uint32_t>)ac;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = w[i];
+    return ac == a4;
+}
+
+// big-endian key lanes (W <= 2) of the L <= 12 bytes held in q from byte sh
+__device__ __forceinline__ void short_word_lanes(const uint32_t (&q)[4], int sh, int L,
+                                                 uint64_t& l0, uint64_t& l1) {
+    uint32_t be[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        uint32_t v = __builtin_bswap32(__builtin_amdgcn_alignbyte(q[i + 1], q[i], sh));
+        const int valid = L - 4 * i;
+        v = valid >= 4 ? v : (valid <= 0 ? 0u : v & (0xFFFFFFFFu << (8 * (4 - valid))));
+        be[i] = v;
+    }
+    l0 = ((uint64_t)be[0] << 32) | be[1];
+    l1 = (uint64_t)be[2] << 32;
+}
+
 // Stable placement by length: a word's place in its list's sub-array is the
 // sub-array start, the words of that length in earlier chunks, and the
 // earlier lanes of this chunk with the same length.  Writes order, or in the
 // batched form (kJobFusedPack) the word's key lanes and index payload at that
-// place directly.
+// place directly.  Rounds are handled kScatterBatch at a time: all their
+// offsets and word bytes are loaded before any of their results is stored.
+constexpr int kScatterBatch = 8;
+
 __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ J) {
     __shared__ int run[kTileWavesPerBlock][kMaxLen + 1];
+    __shared__ int sts[kTileWavesPerBlock][kMaxLen + 1];
     __shared__ int nbs[kTileWavesPerBlock][kMaxLen + 1];
     __shared__ int64_t kos[kTileWavesPerBlock][kMaxLen + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -160,62 +231,129 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ J) {
     int r;
     int64_t a, b, gs, ge;
     if (!chunk_range(J, c, r, a, b, gs, ge)) return;
-    const int ml1 = J->ml1;
+    const int ml1 = J->ml1, max_len = J->max_len;
     const bool fused = (J->flags & kJobFusedPack) != 0;
-    const int32_t* st = J->starts + (int64_t)r * (ml1 + 1);
-    for (int L = lane; L < ml1; L += kWave) {
-        run[wv][L] = st[L] + J->chunk_hist[c * ml1 + L];
-        if (fused) {
-            nbs[wv][L] = J->counts[(int64_t)r * ml1 + L];
-            kos[wv][L] = J->key_off[(int64_t)r * ml1 + L];
+    // the four-dword word loads need at least 16 readable bytes
+    const bool short_words = max_len <= 12;
+    const int64_t n_bytes = J->n_bytes;
+    const int64_t nr = b - a;
+    const int wmax = lanes_for_len(max_len);
+    {
+        const gptr<const int32_t> st = gp(J->starts) + (int64_t)r * (ml1 + 1);
+        const gptr<const int32_t> cnt = gp(J->counts) + (int64_t)r * ml1;
+        const gptr<const int64_t> ko_r = gp(J->key_off) + (int64_t)r * ml1;
+        const gptr<const int32_t> ch = gp(J->chunk_hist) + c * ml1;
+        for (int L = lane; L < ml1; L += kWave) {
+            const int s0 = st[L];
+            run[wv][L] = s0 + ch[L];
+            sts[wv][L] = s0;
+            nbs[wv][L] = fused ? cnt[L] : 0;
+            // a sub-array whose key lanes would leave the list's range is
+            // never written (marked by a negative offset)
+            const int64_t ko = fused ? ko_r[L] : 0;
+            const bool kok = !fused || (ko >= (int64_t)wmax * a &&
+                                        ko + (int64_t)lanes_for_len(L) * cnt[L] <= (int64_t)wmax * b);
+            kos[wv][L] = kok ? ko : -1;
         }
     }
     __builtin_amdgcn_wave_barrier();
-    const int64_t nr = b - a;
-    const int wmax = lanes_for_len(J->max_len);
-    const int64_t first = J->offsets[0];             // nothing below it is read
-    const uint8_t* blo = J->bytes + (first > 0 ? first : 0);
-    const uint8_t* bhi = J->bytes + J->n_bytes;
+    const gptr<const int64_t> offs = gp(J->offsets);
+    const gptr<const uint8_t> bytes = gp(J->bytes);
+    const gptr<uint64_t> keys = gp(J->keys);
+    const gptr<int32_t> perm = gp(J->perm);
+    const gptr<int32_t> order = gp(J->order);
+    const int64_t first = offs[0];                   // nothing below it is read
+    const gptr<const uint8_t> blo = bytes + (first > 0 ? first : 0);
+    const gptr<const uint8_t> bhi = bytes + n_bytes;
+    const bool short_ok = short_words && (uintptr_t)bhi >= (uintptr_t)blo + 32;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    for (int i = 0; i < kChunkRounds; ++i) {
-        const int64_t g = gs + (int64_t)i * kWave + lane;
-        uint32_t bad = 0;
-        const int L = g < ge ? word_len(J, g, bad) : -1;
-        const bool valid = L >= 0;
-        // lanes holding the same length: match the 7 bits of the length
-        uint64_t m = __ballot(valid);
-        const int key = valid ? L : 127;
+    // bits that tell lengths 0..max_len and "no word" (all ones) apart
+    const int nbits = 32 - __builtin_clz((unsigned)ml1);
+    const int none = (1 << nbits) - 1;
+    uint32_t bad = 0, err = 0;
+    for (int i0 = 0; i0 < kChunkRounds; i0 += kScatterBatch) {
+        // 1. lengths (and for short words the bytes) of the batch's words
+        int Ls[kScatterBatch];
+        int64_t o0[kScatterBatch], o1[kScatterBatch];
+        uint32_t q[kScatterBatch][4];
+        int shs[kScatterBatch];
+        bool qok[kScatterBatch];
+        // loads at in-range indices (a chunk holds at least one word), no
+        // branch around them, so they are all in flight before the first is used
 #pragma unroll
-        for (int bit = 0; bit < 7; ++bit) {
-            const bool on = (key >> bit) & 1;
-            const uint64_t bm = __ballot(on);
-            m &= on ? bm : ~bm;
+        for (int k = 0; k < kScatterBatch; ++k) {
+            const int64_t g = gs + (int64_t)(i0 + k) * kWave + lane;
+            const int64_t gc = g < ge ? g : ge - 1;
+            o0[k] = offs[gc];
+            o1[k] = offs[gc + 1];
         }
-        if (valid) {
-            const int rank = __popcll(m & lt);          // earlier lanes, same length
-            const int base = run[wv][L];
-            const int64_t pos = (int64_t)base + rank;
-            if (pos < 0 || pos >= nr) {
-                set_status(J, ST_OVERFLOW);
-            } else if (!fused) {
-                J->order[a + pos] = (int32_t)(g - a);
-            } else {
-                const int64_t j = pos - st[L];           // place inside the sub-array
-                const int nb = nbs[wv][L];
-                const int64_t ko = kos[wv][L];
-                if (j < 0 || j >= nb || ko < (int64_t)wmax * a ||
-                    ko + (int64_t)lanes_for_len(L) * nb > (int64_t)wmax * b) {
-                    set_status(J, ST_BAD_REQ);
+#pragma unroll
+        for (int k = 0; k < kScatterBatch; ++k) {
+            const int64_t g = gs + (int64_t)(i0 + k) * kWave + lane;
+            Ls[k] = g < ge ? word_len_o(o0[k], o1[k], first, n_bytes, max_len, bad) : -1;
+            qok[k] = false;
+            shs[k] = 0;
+        }
+        // key lanes of the whole batch before any of its stores: the
+        // vector-memory counter also counts stores, so a load consumed after
+        // a store has been issued would wait for that store as well
+        uint64_t l0s[kScatterBatch], l1s[kScatterBatch];
+        if (fused && short_ok) {
+#pragma unroll
+            for (int k = 0; k < kScatterBatch; ++k) {
+                const int64_t oc = o0[k] >= 0 && o0[k] <= n_bytes ? o0[k] : 0;
+                const bool in = load_short_word((uintptr_t)blo, (uintptr_t)bhi,
+                                                (uintptr_t)(bytes + oc), q[k], shs[k]);
+                qok[k] = Ls[k] > 0 && in;
+            }
+#pragma unroll
+            for (int k = 0; k < kScatterBatch; ++k)
+                short_word_lanes(q[k], shs[k], Ls[k], l0s[k], l1s[k]);
+        }
+        // 2. places, in round order (each round's counters feed the next)
+#pragma unroll
+        for (int k = 0; k < kScatterBatch; ++k) {
+            const int64_t g = gs + (int64_t)(i0 + k) * kWave + lane;
+            const int L = Ls[k];
+            const bool valid = L >= 0;
+            const int key = valid ? L : none;
+            uint64_t m = ~0ull;                        // lanes holding the same length
+            for (int bit = 0; bit < nbits; ++bit) {
+                const bool on = (key >> bit) & 1;
+                const uint64_t bm = __ballot(on);
+                m &= on ? bm : ~bm;
+            }
+            const int Lc = valid ? L : 0;
+            const int rank = __popcll(m & lt);         // earlier lanes, same length
+            const int base = run[wv][Lc];
+            const int pos = base + rank;
+            const int j = pos - sts[wv][Lc];           // place inside the sub-array
+            const int nb = nbs[wv][Lc];
+            const int64_t ko = kos[wv][Lc];
+            const bool in_list = pos >= 0 && pos < nr;
+            const bool ok = valid && in_list && (!fused || (j >= 0 && j < nb && ko >= 0));
+            err |= (valid && !in_list) ? ST_OVERFLOW : ((valid && !ok) ? ST_BAD_REQ : 0u);
+            if (ok) {
+                if (!fused) {
+                    order[a + pos] = (int32_t)(g - a);
                 } else {
-                    if (L > 0) pack_word(blo, bhi, J->bytes + J->offsets[g], L, J->keys + ko + j, nb);
-                    J->perm[a + pos] = (int32_t)(g - a);
+                    const gptr<uint64_t> out = keys + ko + j;
+                    if (qok[k]) {
+                        out[0] = l0s[k];
+                        if (L > 8) out[nb] = l1s[k];
+                    } else if (L > 0) {
+                        pack_word(blo, bhi, bytes + o0[k], L, out, nb);
+                    }
+                    perm[a + pos] = (int32_t)(g - a);
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            if (rank == 0) run[wv][L] = base + __popcll(m);
+            if (valid && rank == 0) run[wv][L] = base + __popcll(m);
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
     }
+    (void)bad;                                         // reported by the histogram pass
+    if (err) set_status(J, err);
 }
 
 static inline unsigned grid_for(int64_t items, int per_block) {
@@ -230,13 +368,15 @@ hipError_t launch_set_job(const Job& j, Job* dst, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_plan(const Job* J, bool clear_status, hipStream_t s) {
+hipError_t launch_chunk_plan(const Job* J, const Bounds& b, bool clear_status, hipStream_t s) {
     k_chunk_plan<<<1, 1024, 0, s>>>(J, clear_status ? 1 : 0);
+    if (b.R > 1) k_chunk_lists<<<grid_for(b.R, kTileWavesPerBlock), 256, 0, s>>>(J);
     return hipGetLastError();
 }
 
 hipError_t launch_bucketize(const Job* J, const Bounds& b, hipStream_t s) {
-    k_chunk_plan<<<1, 1024, 0, s>>>(J, 1);
+    hipError_t e = launch_chunk_plan(J, b, true, s);
+    if (e != hipSuccess) return e;
     k_chunk_hist<<<grid_for(b.chunk_cap, kTileWavesPerBlock), 256, 0, s>>>(J);
     k_chunk_scan<<<grid_for((int64_t)b.R * b.ml1, kTileWavesPerBlock), 256, 0, s>>>(J);
     k_bucket_starts<<<grid_for(b.R, kTileWavesPerBlock), 256, 0, s>>>(J);

@@ -408,27 +408,27 @@ __device__ __forceinline__ void lds_key(const uint32_t* lds, int cap, int i, uin
 }
 
 // number of the first `diag` outputs of the pair (lower tile at lo, T
-// records; upper at lo+T, nb records) that come from the lower tile;
-// fixed trip count (T <= 2^logT), no branches
+// records; upper at lo+T, nb records) that come from the lower tile: the
+// number of lower records i with lower[i] <= upper[diag-1-i] (this predicate
+// holds on a prefix).  Shrinking-length search, a fixed trip count (T <=
+// 2^logT), no branches; while len > 0 both probes lie inside their tiles.
 template <int D>
 __device__ __forceinline__ int lds_merge_path(const uint32_t* lds, int cap, int lo, int T,
                                               int logT, int nb, int diag) {
-    int a = diag - nb > 0 ? diag - nb : 0;
-    int b = diag < T ? diag : T;
+    int base = diag - nb > 0 ? diag - nb : 0;
+    int len = (diag < T ? diag : T) - base;
+    const int bq = lo + T + diag - 1;                  // upper index = bq - i
     for (int it = 0; it <= logT; ++it) {
-        const int mid = (a + b) >> 1;
-        const int ia = mid < T ? mid : T - 1;
-        const int jb0 = diag - 1 - mid;
-        const int jb = jb0 < 0 ? 0 : (jb0 < nb ? jb0 : nb - 1);
+        const int half = len >> 1;
+        const int i = base + half;
         uint32_t x[D], y[D];
-        lds_key<D>(lds, cap, lo + ia, x);
-        lds_key<D>(lds, cap, lo + T + jb, y);
-        const bool open = a < b;
-        const bool a_first = !key_gt<D>(x, y);          // lower[mid] <= upper[diag-1-mid]
-        a = (open && a_first) ? mid + 1 : a;
-        b = (open && !a_first) ? mid : b;
+        lds_key<D>(lds, cap, lo + i, x);
+        lds_key<D>(lds, cap, bq - i, y);
+        const bool take = len > 0 && !key_gt<D>(x, y); // lower[i] <= upper[diag-1-i]
+        base = take ? i + 1 : base;
+        len = take ? len - half - 1 : half;
     }
-    return a;
+    return base;
 }
 
 // E outputs of the pair starting at output `diag`; positions are absolute:
@@ -601,10 +601,22 @@ static const BucketLauncher kBucketLaunchers[kNumD] = {
     launch_bucket_d<13>, launch_bucket_d<14>, launch_bucket_d<15>, launch_bucket_d<16>,
     launch_bucket_d<17>};
 
+// workgroups of an in-LDS class that can be resident at once: 256 CUs times
+// the workgroups whose LDS fits a CU's 160 KiB (at most 4); a larger grid
+// only adds dispatches, the kernel strides over its list
+template <int D, int C>
+constexpr int64_t lds_resident_groups() {
+    int per_cu = (160 * 1024) / (D * 4 * lds_cap(C, D));
+    if (per_cu > 4) per_cu = 4;
+    if (per_cu < 1) per_cu = 1;
+    return 256 * per_cu;
+}
+
 template <int D, int C>
 static void launch_lds_class_t(const Job* J, int64_t grid, int list, hipStream_t s) {
     if constexpr (lds_fits(D, C)) {
-        int64_t g = grid < 1024 ? grid : 1024;
+        constexpr int64_t gmax = lds_resident_groups<D, C>();
+        int64_t g = grid < gmax ? grid : gmax;
         if (g < 1) g = 1;
         k_bucket_lds<D, lds_threads(C, D), lds_cap(C, D)><<<(unsigned)g, lds_threads(C, D), 0, s>>>(J, list);
     }

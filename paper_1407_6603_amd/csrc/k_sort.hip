@@ -25,7 +25,9 @@ __global__ __launch_bounds__(256) void k_sort_init(const Job* __restrict__ J) {
     if (i0 < kNumD * kLdsClasses) J->lb_count[i0] = 0;
     if (i0 <= kLdsMaxD) J->hc_count[i0] = 0;
     if (i0 == 0) J->pmax[0] = 0;
-    for (int64_t i = i0; i <= J->phase_cap; i += step) J->mcount[i] = 0;
+    // phase counters in use: every sub-array needs fewer than phase_bound phases
+    const int64_t top = J->phase_bound < J->phase_cap ? J->phase_bound : J->phase_cap;
+    for (int64_t i = i0; i <= top; i += step) J->mcount[i] = 0;
 }
 
 // one wave per list; the workgroup's four waves share one global claim per
@@ -390,7 +392,7 @@ hipError_t launch_merge_one_bucket(const Job* J, const MergeItem& item0, int npa
 
 hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s) {
     if (!b.fused_pack) {
-        hipError_t e = launch_chunk_plan(J, false, s);   // k_pack's chunk map
+        hipError_t e = launch_chunk_plan(J, b, false, s);   // k_pack's chunk map
         if (e != hipSuccess) return e;
     }
     k_sort_init<<<grid_for2((int64_t)b.phase_bound + kNumD + 1, 256, 1024), 256, 0, s>>>(J);
