@@ -220,8 +220,8 @@ __device__ __forceinline__ void phases_int(uint32_t (&r)[K][D], int n) {
 
 // A tile in HBM: key lanes and index payload of bucket words [t0, t0+n).
 struct HbmTile {
-    uint64_t* keys;
-    int32_t* perm;
+    gptr<uint64_t> keys;
+    gptr<int32_t> perm;
     int64_t nbk;
     int t0, n;
     bool write_keys;
@@ -336,7 +336,7 @@ __device__ __forceinline__ void sort_tile_any(const Src& src, int n, int lane) {
 
 template <int D>
 __device__ __forceinline__ void run_tile(const Job* J, const TileDesc& t, bool wk, int lane) {
-    HbmTile src{J->keys + t.key_off, J->perm + t.pos0, t.n_b, t.t0, t.n, wk};
+    HbmTile src{gp(J->keys) + t.key_off, gp(J->perm) + t.pos0, t.n_b, t.t0, t.n, wk};
     sort_tile_any<D, kmax_for(D)>(src, t.n, lane);
 }
 
@@ -532,8 +532,9 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         const LBucket bk = lst[bi];
         const int n = bk.n_b;                          // n <= CAP (checked when listed)
         const int64_t ks = bk.stride;                  // key lane stride
-        uint64_t* keys = J->keys + bk.key_off;
-        int32_t* perm = J->perm + bk.pos0;
+        const gptr<uint64_t> keys = gp(J->keys) + bk.key_off;
+        const gptr<int32_t> perm = gp(J->perm) + bk.pos0;
+#pragma unroll 4
         for (int i = tid; i < n; i += NT) {
 #pragma unroll
             for (int w = 0; w < W; ++w) {
@@ -679,8 +680,8 @@ __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, ui
     const int nb = rest < T ? rest : T;
     const int tot = T + nb;
     const int64_t ks = m.n_b;
-    uint64_t* keys = J->keys + m.key_off + lo;
-    int32_t* perm = J->perm + m.pos0 + lo;
+    const gptr<uint64_t> keys = gp(J->keys) + m.key_off + lo;
+    const gptr<int32_t> perm = gp(J->perm) + m.pos0 + lo;
     if (tid == 0) {                                    // in order across the seam: no moves
         int gt = 0;
         for (int w = 0; w < W; ++w) {
@@ -694,6 +695,7 @@ __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, ui
     }
     __syncthreads();
     if (*sflag == 0) return;                           // uniform
+#pragma unroll 4
     for (int i = tid; i < tot; i += kPairThreads) {
 #pragma unroll
         for (int w = 0; w < W; ++w) {
