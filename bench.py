@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-serial", action="store_true",
+                    help="skip the per-stage timing with every stage on one stream")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving run (its own JSON line)")
     ap.add_argument("--serve-arrivals", type=int, default=0,
@@ -369,6 +371,33 @@ def main():
     bs.check_device_status(ws)
     got = perm.cpu().numpy()
 
+    # ---- per-stage times with each stage alone on the GPU (every stage in
+    # order on one stream); the timed region above runs them side by side
+    serial = None
+    if not args.no_serial:
+        stune = bs.tuning(tile, 0, bs.FLAG_SERIAL_STAGES, hbm_tile)
+        sperm = torch.empty(total, dtype=torch.int32, device=dev)
+        reps = min(max(args.steps, 1), 5)
+        stimers = [bs.StageTimer(max_len, stream) for _ in range(reps)]
+        bs.sort_batch_staged(b_t, o_t, rs_t, batch.req_start, max_len, stimers[0], stune, ws,
+                             out=sperm)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for k in range(reps):
+            bs.sort_batch_staged(b_t, o_t, rs_t, batch.req_start, max_len, stimers[k], stune, ws,
+                                 out=sperm)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        bs.check_device_status(ws)
+        ssum = {}
+        for t in stimers:
+            for name, v in t.ms().items():
+                ssum[name] = ssum.get(name, 0.0) + v
+        serial = {"ms_per_step": ev0.elapsed_time(ev1) / reps, "steps": reps,
+                  "stage_ms": {k: v / reps for k, v in ssum.items()},
+                  "identical": bool(np.array_equal(sperm.cpu().numpy(), got))}
+        del sperm
+
     # ---- the same batch through a captured graph plan (one graph launch per step)
     graph = None
     if not args.no_graph:
@@ -413,11 +442,16 @@ def main():
     # every tile and in-LDS stage is exactly one kernel launch)
     struct, merge_bytes, phases_max = workload_structure(
         batch.offsets, batch.req_start, max_len, tile or 256, 2048)
-    # stages run side by side after the pack; the dominant kernel is the one
-    # with the longest launch among stages that have work on this input
+    # stages run side by side after the pack, so a launch's duration in the
+    # timed region includes waiting for CUs that other stages hold (the short
+    # tile sorts queue behind the in-LDS classes).  The dominant kernel is the
+    # one with the most work: the longest launch with the GPU to itself (the
+    # serial leg), among stages that have work on this input; its rate below
+    # uses its launch duration in the timed region.
     worked = {k: v for k, v in stage_ms.items()
               if k in struct or (k == "merge_split" and merge_bytes)}
-    dom = max(worked, key=worked.get)
+    alone = serial["stage_ms"] if serial else stage_ms
+    dom = max(worked, key=lambda k: alone.get(k, 0.0))
     roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": None, "traffic": None}
     if dom in struct:
@@ -430,7 +464,8 @@ def main():
                 "traffic": measured_traffic(kernel_name(dom)),
                 # key lanes (8 B each) read, perm read and written (4 + 4 B) per word
                 "hbm_bytes_algorithmic": (8 * (D // 2) + 8) * w["words"],
-                "launch_ms": stage_ms[dom], "ce_per_launch": ce,
+                "launch_ms": stage_ms[dom], "launch_ms_alone": alone.get(dom),
+                "ce_per_launch": ce,
                 "ce_per_s": ce / sec, "ops_per_ce": 3 * D, "words_per_launch": w["words"]}
         # the compare-exchange roofline as an LDS stream: each CE reads and
         # writes two (key, index) records, 4 * 4D bytes
@@ -493,6 +528,7 @@ def main():
         "per_bucket_launch": plain,
         "batched_over_per_bucket": (value / plain["value"]) if plain else None,
         "stage_ms": stage_ms,
+        "serial_stages": serial,
         "merge_phases_max": phases_max,
         "work": struct,
         "roofline": roof,

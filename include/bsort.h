@@ -104,6 +104,11 @@ typedef struct {
 /* Testing only: stop after the tile sorts (no merge-split); perm then holds
  * each tile sorted on its own. */
 #define BSORT_FLAG_TILES_ONLY 2
+/* Run every sort stage in order on the caller's stream instead of fanning
+ * the in-LDS classes out over the library's own streams.  Same result;
+ * slower, but each stage then has the GPU to itself (per-stage timing) and
+ * no work runs outside the caller's stream. */
+#define BSORT_FLAG_SERIAL_STAGES 4
 
 /* Workspace bytes for up to total_words words in up to n_requests lists with
  * words of at most max_len bytes.  Returns 0 for invalid arguments. */
@@ -165,9 +170,12 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
  *
  * bucketize and pack run in order on the caller's stream, then the tile
  * stages and merge_split, in that order (merge_split merges the tiles the
- * tile stages sort).  The in-LDS stages touch sub-arrays of their own and
- * run concurrently with those on three library streams (default priority),
- * joined back into the caller's stream before the call's work ends.
+ * tile stages sort).  The in-LDS stages touch sub-arrays of their own; they
+ * are queued after the tile stages and run concurrently with them and with
+ * merge_split on three library streams (default priority), joined back into
+ * the caller's stream before the call's work ends.  With
+ * BSORT_FLAG_SERIAL_STAGES every stage runs on the caller's stream in the
+ * order tiles, in-LDS classes, merge_split.
  *
  * bsort_sort_batch_staged is bsort_sort_batch that also records the caller's
  * HIP events (hipEvent_t passed as void*): events[2i] just before stage i and

@@ -19,6 +19,7 @@ STATUS = {0: "BSORT_OK", 1: "BSORT_E_INVALID", 2: "BSORT_E_TOO_LONG", 3: "BSORT_
           4: "BSORT_E_WORKSPACE", 5: "BSORT_E_HIP", 6: "BSORT_E_CAPACITY"}
 FLAG_PER_BUCKET_LAUNCH = 1
 FLAG_TILES_ONLY = 2
+FLAG_SERIAL_STAGES = 4
 
 EXPORTS = [
     "bsort_workspace_bytes", "bsort_bucketize", "bsort_sort_buckets", "bsort_sort_batch",

@@ -18,6 +18,7 @@ Tuning = _lib.Tuning
 BsortError = _lib.BsortError
 FLAG_PER_BUCKET_LAUNCH = _lib.FLAG_PER_BUCKET_LAUNCH
 FLAG_TILES_ONLY = _lib.FLAG_TILES_ONLY
+FLAG_SERIAL_STAGES = _lib.FLAG_SERIAL_STAGES
 MAX_LEN = _lib.BSORT_MAX_LEN
 
 

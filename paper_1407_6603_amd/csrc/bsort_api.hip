@@ -103,7 +103,8 @@ bsort_status check_tuning(const bsort_tuning* t) {
     if (t->merge_threads != 0 &&
         (t->merge_threads < 64 || t->merge_threads > 1024 || t->merge_threads % 64))
         return fail(BSORT_E_INVALID, "merge_threads must be 0 or a multiple of 64 in [64, 1024]");
-    if (t->flags & ~(BSORT_FLAG_PER_BUCKET_LAUNCH | BSORT_FLAG_TILES_ONLY))
+    if (t->flags &
+        ~(BSORT_FLAG_PER_BUCKET_LAUNCH | BSORT_FLAG_TILES_ONLY | BSORT_FLAG_SERIAL_STAGES))
         return fail(BSORT_E_INVALID, "unknown flag");
     return BSORT_OK;
 }
@@ -548,23 +549,33 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
             return e;
         if ((e = hipEventRecord(f.pmax_ev, s)) != hipSuccess) return e;
     }
+    const bool fan = !(b.flags & BSORT_FLAG_SERIAL_STAGES);
     hipStream_t st[kFan] = {s, f.aux[0], f.aux[1], f.aux[2]};
-    if ((e = hipEventRecord(f.fork, s)) != hipSuccess) return e;
-    for (int k = 1; k < kFan; ++k)
-        if ((e = hipStreamWaitEvent(st[k], f.fork, 0)) != hipSuccess) return e;
+    if (fan) {
+        if ((e = hipEventRecord(f.fork, s)) != hipSuccess) return e;
+        for (int k = 1; k < kFan; ++k)
+            if ((e = hipStreamWaitEvent(st[k], f.fork, 0)) != hipSuccess) return e;
+    }
     const std::vector<StageRef> stages = sort_stages(b);
-    // in-LDS classes first, round-robin on the library streams
+    // the tile sorts first on the caller's stream (short; the merge-split
+    // waits on them), then the in-LDS classes round-robin on the library
+    // streams, then the merge-split after the tiles on the caller's stream
+    for (const StageRef& g : stages) {
+        if (g.kind != kStageTiles) continue;
+        if ((e = rec(g.index, 0, s)) != hipSuccess) return e;
+        if ((e = run_stage(g, J, b, s, -1)) != hipSuccess) return e;
+        if ((e = rec(g.index, 1, s)) != hipSuccess) return e;
+    }
     int lds_seen = 0;
     for (const StageRef& g : stages) {
         if (g.kind != kStageLds) continue;
-        hipStream_t x = st[1 + (lds_seen++) % (kFan - 1)];
+        hipStream_t x = fan ? st[1 + (lds_seen++) % (kFan - 1)] : s;
         if ((e = rec(g.index, 0, x)) != hipSuccess) return e;
         if ((e = run_stage(g, J, b, x, -1)) != hipSuccess) return e;
         if ((e = rec(g.index, 1, x)) != hipSuccess) return e;
     }
-    // tile sorts, then the merge-split, in order on the caller's stream
     for (const StageRef& g : stages) {
-        if (g.kind == kStageLds) continue;
+        if (g.kind != kStageMerge) continue;
         int phases = -1;
         if (g.kind == kStageMerge && readback) {
             if ((e = hipEventSynchronize(f.pmax_ev)) != hipSuccess) return e;
@@ -574,7 +585,7 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
         if ((e = run_stage(g, J, b, s, phases)) != hipSuccess) return e;
         if ((e = rec(g.index, 1, s)) != hipSuccess) return e;
     }
-    for (int k = 1; k < kFan; ++k) {
+    for (int k = 1; fan && k < kFan; ++k) {
         if ((e = hipEventRecord(f.join[k - 1], st[k])) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(s, f.join[k - 1], 0)) != hipSuccess) return e;
     }

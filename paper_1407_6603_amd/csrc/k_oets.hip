@@ -470,25 +470,120 @@ __host__ __device__ constexpr int merge_slot_outputs(int cap, int nt) {
     return q >= 8 ? 8 : q >= 4 ? 4 : 2;
 }
 
-template <int D, int NT, int CAP>
-__device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, int s, int tid) {
+// Count of records r[0..m) (sorted by key) that come before x: keys <= x
+// when le, keys < x otherwise.  The predicate holds on a prefix, so each
+// round probes the last record of 64 equal cells (one per lane) of the
+// range still open and a ballot's popcount says how many whole cells lie
+// inside the prefix; the next round searches the first cell that does not.
+// T is a power of two >= m; rounds: ceil(log64 T), at least one.
+template <int D>
+__device__ __forceinline__ int wave_count_before(const uint32_t* lds, int cap, int at, int m,
+                                                 int T, const uint32_t (&x)[D], bool le,
+                                                 int lane) {
+    auto pred = [&](int i) -> bool {
+        uint32_t y[D];
+        lds_key<D>(lds, cap, at + (i < m ? i : m - 1), y);
+        const bool before = le ? !key_gt<D>(y, x) : key_gt<D>(x, y);
+        return i < m && before;
+    };
+    int base = 0;
+    for (int step = T >> 6;; step >>= 6) {                // uniform trip count
+        const int st = step > 0 ? step : 1;
+        base += __popcll(__ballot(pred(base + (lane + 1) * st - 1))) * st;
+        if (st == 1) break;
+    }
+    return base;
+}
+
+// per-phase window table in LDS (merge_win_words ints), owned by the kernel
+constexpr int kMaxPairs = 64;                              // 16384 / 128 / 2
+constexpr int kMergeWinWords = 4 * kMaxPairs + 1;
+
+// WIN: trim each pair to its changing window first (two ballot searches and
+// two barriers per phase; pays off where pairs are many and long)
+template <int D, int NT, int CAP, bool WIN>
+__device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, int s, int tid,
+                                int* win) {
     constexpr int E = merge_slot_outputs(CAP, NT);        // outputs per slot
     constexpr int S = (CAP + NT * E - 1) / (NT * E);      // slots per thread
+    constexpr int NW = NT / kWave;
+    static_assert(CAP / 128 / 2 <= kMaxPairs, "pairs per phase");
+    int* wlo = win;
+    int* wna = win + kMaxPairs;
+    int* wnb = win + 2 * kMaxPairs;
+    int* slot0 = win + 3 * kMaxPairs;
     const int off = s & 1;
     if (p - 2 < off) return;                              // no pair in this phase (uniform)
-    const int a_last = p - 2 - ((p - 2 - off) & 1);       // last lower tile of the phase
-    const int U0 = off * T;
-    const int U1 = (a_last + 2) * T < n ? (a_last + 2) * T : n;
-    uint32_t out[S][E][D];
-    int pos[S];
-#pragma unroll
-    for (int r = 0; r < S; ++r) {
-        pos[r] = U0 + (tid + r * NT) * E;
-        if (pos[r] < U1) {
-            const int a = off + (((pos[r] - U0) >> (logT + 1)) << 1);   // pair's lower tile
-            const int lo = a << logT;
+    const int np = (p - 2 - off) / 2 + 1;                 // pairs a = off, off+2, ...
+    const int lane = tid & 63, wv = tid >> 6;
+
+    int total = NT * S + 1;                               // full pairs unless windowed
+    if constexpr (WIN) {
+        // 1. the window of each pair that changes: the lower tile's records above
+        // the upper tile's first key and the upper tile's records below the lower
+        // tile's last key (equal keys: lower tile first).  Records left of it stay.
+        for (int k = wv; k < np; k += NW) {
+            const int lo = (off + 2 * k) << logT;
             const int nb = n - lo - T < T ? n - lo - T : T;
-            lds_merge_slot<D, E>(lds, CAP, n, lo, T, logT, nb, pos[r] - lo, out[r]);
+            uint32_t b0[D], alast[D];
+            lds_key<D>(lds, CAP, lo + T, b0);
+            lds_key<D>(lds, CAP, lo + T - 1, alast);
+            const int j0 = wave_count_before<D>(lds, CAP, lo, T, T, b0, true, lane);
+            const int j1 = wave_count_before<D>(lds, CAP, lo + T, nb, T, alast, false, lane);
+            if (lane == 0) {
+                const bool moves = key_gt<D>(alast, b0);
+                wlo[k] = lo + j0;
+                wna[k] = moves ? T - j0 : 0;
+                wnb[k] = moves ? j1 : 0;
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {                                    // slots per pair, exclusive scan
+            const int w = lane < np ? wna[lane] + wnb[lane] : 0;
+            const int v = (w + E - 1) / E;
+            const int incl = wave_incl_scan(v, lane);
+            if (lane < np) slot0[lane] = incl - v;
+            if (lane == 63) slot0[np] = incl;
+        }
+        __syncthreads();
+        total = slot0[np];
+    }
+    uint32_t out[S][E][D];
+    int pos[S], cnt[S];
+
+    if (total <= NT * S) {
+        // 2. merge the windows only
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            const int q = tid + r * NT;
+            cnt[r] = 0;
+            pos[r] = 0;
+            if (q < total) {
+                int k = 0;                                // pair of slot q
+                for (int h = kMaxPairs / 2; h > 0; h >>= 1)
+                    if (k + h < np && slot0[k + h] <= q) k += h;
+                const int na = wna[k], nbw = wnb[k];
+                const int diag = (q - slot0[k]) * E;
+                pos[r] = wlo[k] + diag;
+                cnt[r] = na + nbw - diag < E ? na + nbw - diag : E;
+                lds_merge_slot<D, E>(lds, CAP, n, wlo[k], na, logT, nbw, diag, out[r]);
+            }
+        }
+    } else {
+        // (per-pair rounding overflowed the slots: merge whole pairs)
+        const int a_last = off + 2 * (np - 1);
+        const int U0 = off * T;
+        const int U1 = (a_last + 2) * T < n ? (a_last + 2) * T : n;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            pos[r] = U0 + (tid + r * NT) * E;
+            cnt[r] = U1 - pos[r] < E ? U1 - pos[r] : E;
+            if (pos[r] < U1) {
+                const int a = off + (((pos[r] - U0) >> (logT + 1)) << 1);   // pair's lower tile
+                const int lo = a << logT;
+                const int nb = n - lo - T < T ? n - lo - T : T;
+                lds_merge_slot<D, E>(lds, CAP, n, lo, T, logT, nb, pos[r] - lo, out[r]);
+            }
         }
     }
     __syncthreads();                                      // every read of this phase is done
@@ -496,7 +591,7 @@ __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, in
     for (int r = 0; r < S; ++r) {
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-            if (pos[r] + j < U1) {
+            if (j < cnt[r]) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) lds[d * CAP + pos[r] + j] = out[r][j][d];
             }
@@ -508,6 +603,7 @@ __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, in
 template <int D, int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, int list) {
     __shared__ uint32_t lds[D * CAP];
+    __shared__ int mwin[CAP >= 8192 ? kMergeWinWords : 1];
     constexpr int NW = NT / kWave;
     constexpr int Dk = D - 1, W = (Dk + 1) / 2;
     constexpr int KCAP = kmax_for(D) < kLdsMaxTile / kWave ? kmax_for(D) : kLdsMaxTile / kWave;
@@ -555,7 +651,7 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         __syncthreads();
         if (!tiles_only)
             for (int s = 0; s < p; ++s)
-                lds_merge_phase<D, NT, CAP>(lds, n, T, logT, p, s, tid);
+                lds_merge_phase<D, NT, CAP, (CAP >= 8192)>(lds, n, T, logT, p, s, tid, mwin);
         for (int i = tid; i < n; i += NT) {
             perm[i] = (int32_t)lds[Dk * CAP + i];
             if (bk.wk) {
@@ -670,8 +766,9 @@ constexpr int kPairThreads = 512;
 // phase of the in-LDS merge-split over a two-tile array.
 template <int D>
 __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, uint32_t* lds,
-                               int* sflag, int tid) {
+                               int* sflag, int* win, int tid) {
     constexpr int CAP2 = pair_cap(D);
+    static_assert(CAP2 * 4 * D <= kLdsBytes - 4 * (kMergeWinWords + 1), "pair merge LDS");
     constexpr int Dk = D - 1, W = (Dk + 1) / 2;
     const int T = m.T;                                 // power of two, 2T <= CAP2
     const int logT = 31 - __builtin_clz(T);
@@ -706,7 +803,7 @@ __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, ui
         lds[Dk * CAP2 + i] = (uint32_t)perm[i];
     }
     __syncthreads();
-    lds_merge_phase<D, kPairThreads, CAP2>(lds, tot, T, logT, 2, 0, tid);
+    lds_merge_phase<D, kPairThreads, CAP2, true>(lds, tot, T, logT, 2, 0, tid, win);
     for (int i = tid; i < tot; i += kPairThreads) {
         perm[i] = (int32_t)lds[Dk * CAP2 + i];
 #pragma unroll
@@ -720,10 +817,10 @@ __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, ui
 
 template <int D>
 __device__ __forceinline__ void merge_pair_d(const Job* J, const MergeItem& m, uint32_t* lds,
-                                             int* sflag, int tid, int d) {
+                                             int* sflag, int* win, int tid, int d) {
     if constexpr (D <= kMaxD) {
-        if (d == D) merge_pair_lds<D>(J, m, lds, sflag, tid);
-        else merge_pair_d<D + 1>(J, m, lds, sflag, tid, d);
+        if (d == D) merge_pair_lds<D>(J, m, lds, sflag, win, tid);
+        else merge_pair_d<D + 1>(J, m, lds, sflag, win, tid, d);
     }
 }
 
@@ -732,6 +829,7 @@ __device__ __forceinline__ void merge_pair_d(const Job* J, const MergeItem& m, u
 __global__ __launch_bounds__(kPairThreads) void k_merge_pairs(const Job* __restrict__ J, int s) {
     extern __shared__ uint32_t lds[];
     __shared__ int sflag;
+    __shared__ int mwin[kMergeWinWords];
     if (s >= J->phase_cap) return;
     int cnt = J->mcount[s];
     if (cnt > J->merge_cap) cnt = (int)J->merge_cap;
@@ -739,7 +837,7 @@ __global__ __launch_bounds__(kPairThreads) void k_merge_pairs(const Job* __restr
     const int tid = threadIdx.x;
     for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
         const MergeItem m = items[it];
-        merge_pair_d<2>(J, m, lds, &sflag, tid, dwords_for_len(m.L));
+        merge_pair_d<2>(J, m, lds, &sflag, mwin, tid, dwords_for_len(m.L));
         if (tid == 0 && s + 1 < m.p) {
             // successors: pair (a+1, a+2); after an odd phase also (0, 1)
             if (m.a + 2 < m.p) {
@@ -765,7 +863,8 @@ int pair_merge_lds(int dmax) {
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)k_merge_pairs,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kLdsBytes - 4 * (kMergeWinWords + 1));
         attr = true;
     }
     return need;

@@ -332,6 +332,18 @@ def test_plain_per_bucket_form_equals_batched(bs, ws, batch_small):
     assert np.array_equal(batched, expect)
 
 
+def test_serial_stages_equal_fanned_out(bs, ws, batch_small):
+    """Every stage on the caller's stream gives the same bits as the default
+    fan-out over the library's streams, on a batch and on a list whose
+    largest sub-arrays merge through HBM."""
+    fanned = gpu_batch(bs, ws, batch_small, 12)
+    serial = gpu_batch(bs, ws, batch_small, 12, tune=bs.tuning(0, 0, bs.FLAG_SERIAL_STAGES))
+    assert np.array_equal(serial, fanned)
+    w = wordgen.single(3)
+    got = gpu_sort(bs, ws, w, 24, tune=bs.tuning(0, 0, bs.FLAG_SERIAL_STAGES))
+    assert np.array_equal(got, oracle.definition_sort(w.bytes, w.offsets))
+
+
 def test_plan_replays_on_new_batches(bs, batch_small):
     """A captured plan run twice in a row, the second time on a smaller batch
     with other buffers; each result equals the oracle."""
