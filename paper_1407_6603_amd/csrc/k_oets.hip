@@ -269,8 +269,14 @@ struct HbmTile {
     }
 };
 
-// A tile of records held in LDS as SoA dwords (dword d of record i at
-// lds[d*cap + i]), records [t0, t0+n).
+// Records in LDS are SoA dword planes of `cap` (a multiple of 64) records:
+// dword d of record i sits at lds[d*cap + lsw(i)].  lsw permutes the records
+// inside each row of 64 (column XOR row), so lanes that touch records a
+// multiple of 2..64 apart, as tile loads (K per lane) and slot write-backs
+// (E per lane) do, spread over the banks instead of a few of them.
+__device__ __forceinline__ int lsw(int i) { return i ^ ((i >> 6) & 63); }
+
+// A tile of records held in LDS, records [t0, t0+n).
 struct LdsTile {
     uint32_t* lds;
     int cap;
@@ -283,7 +289,7 @@ struct LdsTile {
         for (int k = 0; k < K; ++k) {
             const int j = jbase + k;
 #pragma unroll
-            for (int d = 0; d < D; ++d) r[k][d] = j < jend ? lds[d * cap + j] : 0xFFFFFFFFu;
+            for (int d = 0; d < D; ++d) r[k][d] = j < jend ? lds[d * cap + lsw(j)] : 0xFFFFFFFFu;
         }
     }
     template <int D, int K>
@@ -294,7 +300,7 @@ struct LdsTile {
             const int j = jbase + k;
             if (j < jend) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) lds[d * cap + j] = r[k][d];
+                for (int d = 0; d < D; ++d) lds[d * cap + lsw(j)] = r[k][d];
             }
         }
     }
@@ -379,8 +385,9 @@ __global__ __launch_bounds__(64) void k_oets_bucket(const Job* __restrict__ J, T
 
 template <int D>
 __device__ __forceinline__ void lds_rec(const uint32_t* lds, int cap, int i, uint32_t (&x)[D]) {
+    const int a = lsw(i);
 #pragma unroll
-    for (int d = 0; d < D; ++d) x[d] = lds[d * cap + i];
+    for (int d = 0; d < D; ++d) x[d] = lds[d * cap + a];
 }
 
 // ---- merge-split phases inside LDS
@@ -402,8 +409,9 @@ __device__ __forceinline__ void lds_rec(const uint32_t* lds, int cap, int i, uin
 
 template <int D>
 __device__ __forceinline__ void lds_key(const uint32_t* lds, int cap, int i, uint32_t (&x)[D]) {
+    const int a = lsw(i);
 #pragma unroll
-    for (int d = 0; d < D - 1; ++d) x[d] = lds[d * cap + i];
+    for (int d = 0; d < D - 1; ++d) x[d] = lds[d * cap + a];
     x[D - 1] = 0;
 }
 
@@ -592,8 +600,9 @@ __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, in
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             if (j < cnt[r]) {
+                const int a = lsw(pos[r] + j);
 #pragma unroll
-                for (int d = 0; d < D; ++d) lds[d * CAP + pos[r] + j] = out[r][j][d];
+                for (int d = 0; d < D; ++d) lds[d * CAP + a] = out[r][j][d];
             }
         }
     }
@@ -608,6 +617,7 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
     constexpr int Dk = D - 1, W = (Dk + 1) / 2;
     constexpr int KCAP = kmax_for(D) < kLdsMaxTile / kWave ? kmax_for(D) : kLdsMaxTile / kWave;
     static_assert(D * CAP * 4 <= kLdsBytes, "sub-array does not fit the LDS budget");
+    static_assert(CAP % 64 == 0, "lsw permutes whole rows of 64 records");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // list < kLdsClasses: the sub-arrays of that size class; list ==
     // kLdsClasses: chunks of sub-arrays that are merged through HBM next
@@ -632,13 +642,14 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         const gptr<int32_t> perm = gp(J->perm) + bk.pos0;
 #pragma unroll 4
         for (int i = tid; i < n; i += NT) {
+            const int a = lsw(i);
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 const uint64_t v = keys[w * ks + i];
-                lds[(2 * w) * CAP + i] = (uint32_t)(v >> 32);
-                if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + i] = (uint32_t)v;
+                lds[(2 * w) * CAP + a] = (uint32_t)(v >> 32);
+                if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + a] = (uint32_t)v;
             }
-            lds[Dk * CAP + i] = (uint32_t)perm[i];
+            lds[Dk * CAP + a] = (uint32_t)perm[i];
         }
         __syncthreads();
         const int p = (n + T - 1) / T;
@@ -653,12 +664,13 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
             for (int s = 0; s < p; ++s)
                 lds_merge_phase<D, NT, CAP, (CAP >= 8192)>(lds, n, T, logT, p, s, tid, mwin);
         for (int i = tid; i < n; i += NT) {
-            perm[i] = (int32_t)lds[Dk * CAP + i];
+            const int a = lsw(i);
+            perm[i] = (int32_t)lds[Dk * CAP + a];
             if (bk.wk) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    const uint64_t hi = lds[(2 * w) * CAP + i];
-                    const uint64_t lo = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP + i] : 0u;
+                    const uint64_t hi = lds[(2 * w) * CAP + a];
+                    const uint64_t lo = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP + a] : 0u;
                     keys[w * ks + i] = (hi << 32) | lo;
                 }
             }
@@ -769,6 +781,7 @@ __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, ui
                                int* sflag, int* win, int tid) {
     constexpr int CAP2 = pair_cap(D);
     static_assert(CAP2 * 4 * D <= kLdsBytes - 4 * (kMergeWinWords + 1), "pair merge LDS");
+    static_assert(CAP2 % 64 == 0, "lsw permutes whole rows of 64 records");
     constexpr int Dk = D - 1, W = (Dk + 1) / 2;
     const int T = m.T;                                 // power of two, 2T <= CAP2
     const int logT = 31 - __builtin_clz(T);
@@ -794,22 +807,24 @@ __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, ui
     if (*sflag == 0) return;                           // uniform
 #pragma unroll 4
     for (int i = tid; i < tot; i += kPairThreads) {
+        const int a = lsw(i);
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             const uint64_t v = keys[w * ks + i];
-            lds[(2 * w) * CAP2 + i] = (uint32_t)(v >> 32);
-            if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP2 + i] = (uint32_t)v;
+            lds[(2 * w) * CAP2 + a] = (uint32_t)(v >> 32);
+            if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP2 + a] = (uint32_t)v;
         }
-        lds[Dk * CAP2 + i] = (uint32_t)perm[i];
+        lds[Dk * CAP2 + a] = (uint32_t)perm[i];
     }
     __syncthreads();
     lds_merge_phase<D, kPairThreads, CAP2, true>(lds, tot, T, logT, 2, 0, tid, win);
     for (int i = tid; i < tot; i += kPairThreads) {
-        perm[i] = (int32_t)lds[Dk * CAP2 + i];
+        const int a = lsw(i);
+        perm[i] = (int32_t)lds[Dk * CAP2 + a];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            const uint64_t hi = lds[(2 * w) * CAP2 + i];
-            const uint64_t lo32 = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP2 + i] : 0u;
+            const uint64_t hi = lds[(2 * w) * CAP2 + a];
+            const uint64_t lo32 = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP2 + a] : 0u;
             keys[w * ks + i] = (hi << 32) | lo32;
         }
     }
