@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-tokenize", action="store_true",
+                    help="skip the raw-text pre-processing leg")
     ap.add_argument("--no-serial", action="store_true",
                     help="skip the per-stage timing with every stage on one stream")
     ap.add_argument("--serve-only", action="store_true",
@@ -312,6 +314,9 @@ def main():
         print(json.dumps(serve_line(sw, args, time.time() - t0)), flush=True)
         return
     batch = wordgen.batch(workers=args.gen_workers)
+    text = None
+    if not args.no_tokenize:
+        text = wordgen.raw_text(wordgen.Words(batch.bytes, batch.offsets), seed=4)
     gen_s = time.time() - t0
     max_len = 12
     total = batch.total
@@ -438,6 +443,37 @@ def main():
                  "identical_to_batched": same}
         del pws, pperm
 
+    # ---- pre-processing leg: the batch's words as one raw text (separators
+    # of TEXT_SEPARATORS), tokenized back into words
+    tok = None
+    if text is not None:
+        text_t = torch.from_numpy(text).to(dev)
+        tws = bs.Workspace(device=dev)
+        words_t, offsets_t, res_t = bs.tokenize(text_t, ws=tws, sync=False)
+        torch.cuda.synchronize()
+        reps = max(args.steps, 1)
+        ev0.record(stream)
+        for _ in range(reps):
+            bs.tokenize(text_t, ws=tws, sync=False)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t_ms = ev0.elapsed_time(ev1) / reps
+        nw, nl, ml, st = (int(x) for x in res_t.cpu())
+        same = (st == 0 and nw == total
+                and bool(np.array_equal(offsets_t[:nw + 1].cpu().numpy(), batch.offsets))
+                and bool(np.array_equal(words_t[:nl].cpu().numpy(), batch.bytes)))
+        # algorithmic HBM bytes: the text read once, the letters and the
+        # int64 offsets written once
+        tb = len(text) + nl + 8 * (nw + 1)
+        gbs = tb / (t_ms / 1e3) / 1e9
+        tok = {"text_bytes": len(text), "words": nw, "letters": nl, "max_len": ml,
+               "ms": t_ms, "words_per_s": nw / (t_ms / 1e3), "text_gb_per_s": len(text) / t_ms / 1e6,
+               "identical_to_batch_words": same,
+               "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": gbs / PEAK_HBM_GBS, "bytes_algorithmic": tb,
+                            "kernels": "k_tok_count, k_tok_scan, k_tok_write, k_tok_maxlen"}}
+        del text_t, tws, words_t, offsets_t, res_t
+
     # ---- roofline of the dominant kernel (the stage with the largest time;
     # every tile and in-LDS stage is exactly one kernel launch)
     struct, merge_bytes, phases_max = workload_structure(
@@ -529,6 +565,7 @@ def main():
         "batched_over_per_bucket": (value / plain["value"]) if plain else None,
         "stage_ms": stage_ms,
         "serial_stages": serial,
+        "tokenize": tok,
         "merge_phases_max": phases_max,
         "work": struct,
         "roofline": roof,

@@ -191,6 +191,39 @@ bsort_status bsort_sort_batch_staged(const bsort_batch *b, int32_t *perm, const 
                                      void *const *events, int n_events);
 
 /*
+ * Pre-processing (Section II phase 1, Section III approach one step 2):
+ * raw text to words.  The paper removes special characters (quote, comma,
+ * full stop, question and exclamation marks, ...) and splits the text into
+ * words; here a word is a maximal run of ASCII letters [A-Za-z] and every
+ * other byte (space, newline, punctuation, digits, bytes >= 0x80) separates
+ * words and is dropped.  Words keep their text order and case.
+ *
+ *   text         device [n_bytes], any alignment; only these bytes are read
+ *   words_out    device [n_bytes]: the words' letters back to back (the
+ *                first result[1] bytes are written)
+ *   offsets_out  device [cap_words + 1]: word i is
+ *                words_out[offsets_out[i] .. offsets_out[i+1]), i < result[0]
+ *   cap_words    capacity of offsets_out in words; (n_bytes + 1) / 2 always
+ *                suffices (a word is at least one letter and a separator)
+ *   result       device int64[4], written by the call's stream work:
+ *                [0] number of words, [1] number of letters, [2] longest
+ *                word in bytes, [3] BSORT_OK or BSORT_E_CAPACITY when
+ *                result[0] > cap_words (then only offsets_out[0 .. cap_words)
+ *                are written; the counts and result[2] still cover every word)
+ *   ws           at least bsort_tokenize_workspace_bytes(n_bytes) bytes,
+ *                256-byte aligned
+ *
+ * The output feeds bsort_bucketize, bsort_sort_buckets and bsort_sort_batch
+ * as is (bytes = words_out, offsets = offsets_out, n_words = result[0],
+ * max_len >= result[2]).
+ * n_bytes == 0 gives no words (offsets_out[0] = 0).
+ */
+size_t bsort_tokenize_workspace_bytes(int64_t n_bytes);
+bsort_status bsort_tokenize(const uint8_t *text, int64_t n_bytes, uint8_t *words_out,
+                            int64_t *offsets_out, int64_t cap_words, int64_t *result, void *ws,
+                            size_t ws_bytes, bsort_stream_t stream);
+
+/*
  * A captured batch: bsort_sort_batch's launches recorded once into a HIP
  * graph for batches within the given capacity, then replayed by
  * bsort_plan_execute with one graph launch (plus one small launch that

@@ -19,6 +19,9 @@ Contents
   sub-array contents (the paper's count array and sub-array fill).
 * ``pack_keys`` -- fixed-width big-endian uint64 key lanes of equal-length
   words (Section III approach two: one fixed width per sub-array).
+* ``tokenize`` -- Section II pre-processing phase 1: raw text to words,
+  a word being a maximal run of ASCII letters (every other byte, the paper's
+  "special characters" among them, separates words and is dropped).
 * ``brute_force`` -- pure Python, tiny inputs only: tries every permutation
   and returns the unique one along which (length, bytes, index) strictly
   increases.
@@ -92,9 +95,10 @@ def _load(path: str):
     L.oracle_definition_sort_batch.argtypes = [P, i64, P, P, i32, ctypes.c_int, P]
     L.oracle_pack_keys.argtypes = [P, P, P, i32, i32, P]
     L.oracle_max_threads.argtypes = []
+    L.oracle_tokenize.argtypes = [P, i64, P, P, i64, P, P]
     for f in (L.oracle_bucketize, L.oracle_bubble_sort, L.oracle_bubble_sort_batch,
               L.oracle_definition_sort, L.oracle_definition_sort_batch, L.oracle_pack_keys,
-              L.oracle_max_threads):
+              L.oracle_max_threads, L.oracle_tokenize):
         f.restype = ctypes.c_int
     return L
 
@@ -125,6 +129,23 @@ def _check(rc: int, what: str):
 
 def default_max_len(offsets: np.ndarray) -> int:
     return int(np.diff(offsets).max()) if len(offsets) > 1 else 0
+
+
+def tokenize(text) -> Tuple[np.ndarray, np.ndarray]:
+    """Section II pre-processing phase 1: raw text (bytes or uint8 array) ->
+    (letters of the words back to back, int64 offsets[n_words + 1]).  A word
+    is a maximal run of ASCII letters; every other byte is dropped."""
+    t = np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray)) \
+        else np.ascontiguousarray(text, dtype=np.uint8)
+    n = t.size
+    src = t if n else np.zeros(1, dtype=np.uint8)
+    out = np.zeros(max(n, 1), dtype=np.uint8)
+    cap = (n + 1) // 2
+    offsets = np.zeros(cap + 1, dtype=np.int64)
+    nw, nl = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().oracle_tokenize(_ptr(src), n, _ptr(out), _ptr(offsets), cap,
+                                 ctypes.byref(nw), ctypes.byref(nl)), "tokenize")
+    return out[:nl.value].copy(), offsets[:nw.value + 1].copy()
 
 
 def bucketize(bytes_, offsets, max_len: Optional[int] = None):

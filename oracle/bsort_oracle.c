@@ -294,6 +294,48 @@ int oracle_pack_keys(const uint8_t *bytes, const int64_t *offsets, const int32_t
     return ORACLE_OK;
 }
 
+/*
+ * Section II pre-processing phase 1 (Section III approach one step 2): the
+ * special characters are removed and the text is split into words.  Reading
+ * where the paper only gives examples (quote, comma, full stop, question and
+ * exclamation marks): a word is a maximal run of ASCII letters A-Z, a-z, and
+ * every other byte separates words and is dropped.
+ *
+ * One pass over the text: a letter is copied to out; the first letter after a
+ * non-letter (or at the start) opens a new word at the current output
+ * length.  out holds n_bytes bytes, offsets cap_words + 1 entries.  Returns
+ * the word count through *n_words and the letter count through *n_letters;
+ * ORACLE_E_INVALID if the words do not fit cap_words.
+ */
+static int is_ascii_letter(uint8_t c)
+{
+    return (c >= 'A' && c <= 'Z') || (c >= 'a' && c <= 'z');
+}
+
+int oracle_tokenize(const uint8_t *text, int64_t n_bytes, uint8_t *out, int64_t *offsets,
+                    int64_t cap_words, int64_t *n_words, int64_t *n_letters)
+{
+    int64_t nw = 0, nl = 0;
+    int in_word = 0;
+    for (int64_t i = 0; i < n_bytes; ++i) {
+        const uint8_t c = text[i];
+        if (is_ascii_letter(c)) {
+            if (!in_word) {
+                if (nw >= cap_words) return ORACLE_E_INVALID;
+                offsets[nw++] = nl;
+                in_word = 1;
+            }
+            out[nl++] = c;
+        } else {
+            in_word = 0;
+        }
+    }
+    offsets[nw] = nl;
+    *n_words = nw;
+    *n_letters = nl;
+    return ORACLE_OK;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

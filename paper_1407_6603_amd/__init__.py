@@ -6,10 +6,10 @@ streams, and every step of the sort runs in the library's kernels.
 """
 from .api import (BsortError, FLAG_PER_BUCKET_LAUNCH, FLAG_SERIAL_STAGES, FLAG_TILES_ONLY, MAX_LEN, StageTimer, Plan, Tuning,
                   Workspace, bucketize, check_device_status, device_status, sort, sort_batch,
-                  sort_batch_staged, sort_buckets, stage_names, to_device, tuning,
-                  workspace_bytes)
+                  sort_batch_staged, sort_buckets, sort_text, stage_names, to_device, tokenize,
+                  tuning, workspace_bytes)
 
 __all__ = ["BsortError", "FLAG_PER_BUCKET_LAUNCH", "FLAG_SERIAL_STAGES", "FLAG_TILES_ONLY", "StageTimer", "MAX_LEN", "Plan", "Tuning",
            "Workspace", "bucketize", "check_device_status", "device_status", "sort", "sort_batch",
-           "sort_batch_staged", "sort_buckets", "stage_names", "to_device", "tuning",
-           "workspace_bytes"]
+           "sort_batch_staged", "sort_buckets", "sort_text", "stage_names", "to_device",
+           "tokenize", "tuning", "workspace_bytes"]

@@ -26,7 +26,7 @@ EXPORTS = [
     "bsort_plan_create", "bsort_plan_workspace_bytes", "bsort_plan_execute",
     "bsort_plan_destroy", "bsort_stage_count", "bsort_stage_name", "bsort_sort_batch_staged",
     "bsort_get_device_status", "bsort_status_string",
-    "bsort_last_error", "bsort_version",
+    "bsort_last_error", "bsort_version", "bsort_tokenize_workspace_bytes", "bsort_tokenize",
 ]
 
 
@@ -93,6 +93,10 @@ def load(path: str = LIB_PATH):
                                           sz, P, ctypes.POINTER(P), ctypes.c_int]
     L.bsort_sort_batch_staged.restype = ctypes.c_int
     L.bsort_get_device_status.argtypes = [P, P]
+    L.bsort_tokenize_workspace_bytes.argtypes = [i64]
+    L.bsort_tokenize_workspace_bytes.restype = sz
+    L.bsort_tokenize.argtypes = [P, i64, P, P, i64, P, P, sz, P]
+    L.bsort_tokenize.restype = ctypes.c_int
     for f in (L.bsort_bucketize, L.bsort_sort_buckets, L.bsort_sort_batch,
               L.bsort_plan_create, L.bsort_plan_execute, L.bsort_get_device_status):
         f.restype = ctypes.c_int

@@ -137,6 +137,52 @@ def sort(bytes_t: torch.Tensor, offsets_t: torch.Tensor, max_len: int,
     return sort_buckets(bytes_t, offsets_t, counts, starts, order, max_len, tune, ws, stream)
 
 
+def tokenize(text_t: torch.Tensor, ws: Optional[Workspace] = None, cap_words: Optional[int] = None,
+             stream=None, sync: bool = True):
+    """Raw text (uint8 device tensor) -> words: maximal runs of ASCII letters,
+    every other byte dropped (Section II pre-processing phase 1).
+
+    Returns (bytes_t, offsets_t, max_len).  With sync (the default) the
+    call waits for the stream, reads the word count back and returns views
+    of exactly the words; with sync=False it returns the full-capacity
+    buffers and the device int64[4] result (words, letters, longest word,
+    status) instead of max_len."""
+    _require_gpu()
+    if text_t.dtype != torch.uint8 or text_t.dim() != 1 or not text_t.is_cuda:
+        raise ValueError("text must be a 1-D uint8 CUDA tensor")
+    if not text_t.is_contiguous():
+        raise ValueError("text must be contiguous")
+    n = text_t.numel()
+    dev = text_t.device
+    cap = (n + 1) // 2 if cap_words is None else int(cap_words)
+    words = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    offsets = torch.empty(cap + 1, dtype=torch.int64, device=dev)
+    result = torch.empty(4, dtype=torch.int64, device=dev)
+    L = _lib.load()
+    ws = _ws_for(ws, L.bsort_tokenize_workspace_bytes(n), dev)
+    _lib.check(L.bsort_tokenize(_ptr(text_t) if n else None, n, _ptr(words), _ptr(offsets), cap,
+                                _ptr(result), ws.ptr, ws.nbytes, _stream(stream)))
+    if not sync:
+        return words, offsets, result
+    nw, nl, ml, st = (int(x) for x in result.cpu())
+    if st != 0:
+        raise _lib.BsortError(st, f"{nw} words exceed cap_words={cap}")
+    return words[:nl], offsets[:nw + 1], ml
+
+
+def sort_text(text_t: torch.Tensor, tune: Optional[Tuning] = None,
+              ws: Optional[Workspace] = None, stream=None):
+    """The paper's three phases on raw text: tokenize, then sort the words
+    by (length, bytes).  Returns (bytes_t, offsets_t, perm_t)."""
+    words, offsets, ml = tokenize(text_t, ws=ws, stream=stream)
+    if offsets.numel() == 1:
+        return words, offsets, torch.empty(0, dtype=torch.int32, device=text_t.device)
+    if ml > MAX_LEN:
+        raise _lib.BsortError(2, f"a word of {ml} bytes exceeds the {MAX_LEN}-byte limit")
+    perm = sort(words, offsets, max(ml, 1), tune=tune, ws=ws, stream=stream)
+    return words, offsets, perm
+
+
 def sort_batch(bytes_t: torch.Tensor, offsets_t: torch.Tensor, req_start_t: torch.Tensor,
                h_req_start: np.ndarray, max_len: int, tune: Optional[Tuning] = None,
                ws: Optional[Workspace] = None, stream=None,

@@ -267,6 +267,26 @@ size_t bsort_workspace_bytes(int64_t total_words, int32_t max_len, int32_t n_req
     return L.bytes;
 }
 
+size_t bsort_tokenize_workspace_bytes(int64_t n_bytes) {
+    return n_bytes < 0 ? 0 : tok_workspace_bytes(n_bytes);
+}
+
+bsort_status bsort_tokenize(const uint8_t* text, int64_t n_bytes, uint8_t* words_out,
+                            int64_t* offsets_out, int64_t cap_words, int64_t* result, void* ws,
+                            size_t ws_bytes, bsort_stream_t stream) {
+    if (n_bytes < 0 || cap_words < 0) return fail(BSORT_E_INVALID, "negative size");
+    if (!offsets_out || !result) return fail(BSORT_E_INVALID, "offsets_out or result is NULL");
+    if (n_bytes > 0 && (!text || !words_out))
+        return fail(BSORT_E_INVALID, "text or words_out is NULL");
+    if (n_bytes > ((int64_t)1 << 42)) return fail(BSORT_E_INVALID, "text longer than 4 TiB");
+    const size_t need = tok_workspace_bytes(n_bytes);
+    if (!ws || ws_bytes < need) return fail(BSORT_E_WORKSPACE, "workspace too small");
+    if ((uintptr_t)ws & 255) return fail(BSORT_E_WORKSPACE, "workspace not 256-byte aligned");
+    HIP_TRY(launch_tokenize(text, n_bytes, words_out, offsets_out, cap_words, result, ws,
+                            (hipStream_t)stream));
+    return BSORT_OK;
+}
+
 bsort_status bsort_bucketize(const bsort_words* w, const bsort_buckets* b, void* ws,
                              size_t ws_bytes, bsort_stream_t stream) {
     bsort_status st = check_words(w);

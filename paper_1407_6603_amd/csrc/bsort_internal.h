@@ -376,6 +376,11 @@ hipError_t launch_hbm_chunks(const Job* J, const Bounds& b, int D, hipStream_t s
 hipError_t launch_merge_pairs(const Job* J, const Bounds& b, int phase, hipStream_t s);
 // dynamic LDS the batched pair merge needs for records up to dmax dwords
 int pair_merge_lds(int dmax);
+
+// pre-processing, raw text to words (k_tokenize.hip)
+size_t tok_workspace_bytes(int64_t n_bytes);
+hipError_t launch_tokenize(const uint8_t* text, int64_t n_bytes, uint8_t* out, int64_t* offsets,
+                           int64_t cap_words, int64_t* result, void* ws, hipStream_t s);
 // plain per-bucket form pieces
 hipError_t launch_pack(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_tile_one_bucket(const Job* J, int D, const TileDesc& first, int ntiles,

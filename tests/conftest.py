@@ -21,6 +21,16 @@ def oracle_mod():
     return oracle
 
 
+def load_golden_text(name):
+    """The "text <hex>" line of a tests/golden/*.txt fixture (raw text)."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    with open(path) as f:
+        for line in f:
+            if line.startswith("text "):
+                return bytes.fromhex(line.split(" ", 1)[1].strip())
+    raise ValueError(f"{name} has no text line")
+
+
 def load_golden(name):
     """Parse a tests/golden/*.txt hand-worked fixture."""
     path = os.path.join(ROOT, "tests", "golden", name)

@@ -10,7 +10,7 @@ import itertools
 import numpy as np
 
 import wordgen
-from tests.conftest import load_golden
+from tests.conftest import load_golden, load_golden_text
 
 
 def _words(wl):
@@ -154,8 +154,43 @@ def pin_batch_matches_single(oracle):
     return None
 
 
+def pin_tokenize(oracle):
+    """Pre-processing (Section II phase 1), a word being a maximal run of
+    ASCII letters: the hand-worked text gives its sixteen words, and then
+    phases 2-3 give its hand-worked order; random byte strings over all 256
+    values split as the regular expression [A-Za-z]+ splits them (a library
+    routine for the same definition); a seeded raw text made by joining
+    words with separators gives back exactly those words."""
+    import re
+    text = load_golden_text("hand_text.txt")
+    wl, perm, counts = load_golden("hand_text.txt")
+    b, o = oracle.tokenize(text)
+    got = [bytes(b[o[i]:o[i + 1]]) for i in range(len(o) - 1)]
+    if got != wl:
+        return f"hand_text.txt: words {got} != {wl}"
+    if oracle.bubble_sort(b, o).tolist() != perm:
+        return "hand_text.txt: phases 1-3 order differs"
+    rng = np.random.default_rng(17)
+    cases = [b"", b"a", b"-", b"a-", b"-a", b"ab cd", b"@[`{", b"AZaz", b"\x80A\xffz"]
+    for n in (1, 2, 3, 7, 64, 300, 5000):
+        for _ in range(6):
+            cases.append(rng.integers(0, 256, size=n).astype(np.uint8).tobytes())
+            cases.append(rng.choice(np.frombuffer(b"aZ@[`{ .,", np.uint8), size=n).tobytes())
+    for t in cases:
+        expect = re.findall(rb"[A-Za-z]+", t)
+        b, o = oracle.tokenize(t)
+        got = [bytes(b[o[i]:o[i + 1]]) for i in range(len(o) - 1)]
+        if got != expect:
+            return f"tokenize {t[:40]!r}: {got[:5]} != {expect[:5]}"
+    w = wordgen.single(1)
+    b, o = oracle.tokenize(wordgen.raw_text(w, 1))
+    if not (np.array_equal(b, w.bytes) and np.array_equal(o, w.offsets)):
+        return "raw text round trip differs"
+    return None
+
+
 ALL_PINS = [pin_golden, pin_brute_force, pin_library_sort, pin_bucketize_closed_form,
-            pin_comparison_count, pin_pack_closed_form, pin_batch_matches_single]
+            pin_comparison_count, pin_pack_closed_form, pin_batch_matches_single, pin_tokenize]
 
 
 def run_all(oracle):

@@ -119,6 +119,12 @@ MUTANTS = {
                           "starts[L + 1] = starts[L] + counts[L] - (L == 3);"),
     "reverse_index_tiebreak": ("return a < b ? -1 : (a > b ? 1 : 0);",
                                "return a > b ? -1 : (a < b ? 1 : 0);"),
+    "tokenize_bracket_is_letter": ("return (c >= 'A' && c <= 'Z') || (c >= 'a' && c <= 'z');",
+                                   "return (c >= 'A' && c <= '[') || (c >= 'a' && c <= 'z');"),
+    "tokenize_high_bytes_letters": ("return (c >= 'A' && c <= 'Z') || (c >= 'a' && c <= 'z');",
+                                    "return (c >= 'A' && c <= 'Z') || (c >= 'a' && c <= 'z') "
+                                    "|| c >= 0x80;"),
+    "tokenize_no_split": ("            in_word = 0;\n", "            ;\n"),
     "definition_ignores_length": ("if (la != lb) return la < lb ? -1 : 1;",
                                   "if (la != lb) { int q = memcmp(c->bytes + c->offsets[a], "
                                   "c->bytes + c->offsets[b], (size_t)(la < lb ? la : lb)); "

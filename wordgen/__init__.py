@@ -446,3 +446,43 @@ def random_words(rng: np.random.Generator, n: int, lmin: int, lmax: int,
         al = np.frombuffer(alphabet, dtype=np.uint8)
         buf = al[rng.integers(0, len(al), size=total)]
     return Words(buf, offsets)
+
+
+# Separators written after each word of a raw text, with their weights: the
+# paper's examples of special characters (quote, comma, full stop, question
+# and exclamation marks) and other punctuation, line breaks, a tab, a digit
+# and a UTF-8 right single quote.  None holds a letter, so the words of the
+# text are exactly the words it was made from.
+TEXT_SEPARATORS = (
+    (b" ", 0.760), (b", ", 0.070), (b". ", 0.050), (b"\n", 0.040), (b"; ", 0.012),
+    (b": ", 0.008), (b"? ", 0.008), (b"! ", 0.008), (b' "', 0.008), (b'" ', 0.008),
+    (b" -- ", 0.006), (b".\n\n", 0.006), (b"\t", 0.004), (b" 1 ", 0.004),
+    (b"\xe2\x80\x99 ", 0.004), (b"...", 0.004),
+)
+
+
+def raw_text(words: Words, seed: int = 0) -> np.ndarray:
+    """A raw text (uint8) holding `words` in order, each followed by a
+    separator drawn from TEXT_SEPARATORS (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0x7E47])))
+    seps = [np.frombuffer(s, dtype=np.uint8) for s, _ in TEXT_SEPARATORS]
+    w = np.array([p for _, p in TEXT_SEPARATORS], dtype=np.float64)
+    n = words.n
+    kind = rng.choice(len(seps), size=n, p=w / w.sum())
+    sep_len = np.array([len(s) for s in seps], dtype=np.int64)[kind]
+    word_len = np.diff(words.offsets)
+    piece = word_len + sep_len
+    start = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(piece, out=start[1:])
+    out = np.empty(int(start[-1]), dtype=np.uint8)
+    nl = int(words.offsets[-1] - words.offsets[0])
+    if nl:
+        src = words.offsets[0] + np.arange(nl, dtype=np.int64)
+        dst = np.repeat(start[:-1] - words.offsets[:-1], word_len) + src
+        out[dst] = words.bytes[src]
+    for k, s in enumerate(seps):
+        idx = np.nonzero(kind == k)[0]
+        base = start[idx] + word_len[idx]
+        for j in range(len(s)):
+            out[base + j] = s[j]
+    return out
