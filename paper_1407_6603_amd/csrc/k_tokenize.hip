@@ -10,13 +10,15 @@
 // (one workgroup of 256 threads, 64 consecutive bytes per thread read with
 // four 16-byte loads; a thread's letters form one 64-bit mask):
 //   count   per tile: letters, word starts (a letter whose previous byte is
-//           not one), and the letter runs at its two ends and inside it;
+//           not one), and the letters before its first and after its last
+//           word start;
 //   scan    one workgroup: exclusive prefix of letters and words over the
 //           tiles, the totals, the closing offset, and the longest word
-//           (the runs of all tiles joined in order);
-//   write   per tile again: block scans give each thread its letter and
+//           that reaches past a tile's end (tiles joined in text order);
+//   write   per tile again: a block scan gives each thread its letter and
 //           word ranks; letters and word starts are compacted through LDS
-//           and stored in order (letters as aligned dwords).
+//           and stored in order (letters as aligned dwords), and the
+//           longest word inside the tile is folded into the result.
 // The text pointer may have any alignment: tiles are laid over the text
 // rounded down to 16 bytes, interior 16-byte chunks are read with one load,
 // and chunks at either end byte by byte inside the text only.
@@ -33,6 +35,7 @@ constexpr int kTokSpan = kTokBytes * kTokLoads;        // 64 consecutive text by
 constexpr int kTokTile = kTokThreads * kTokSpan;       // 16 KiB of text per workgroup
 constexpr int kTokWaves = kTokThreads / kWave;
 constexpr int kTokScanThreads = 1024;
+constexpr int kTokCountTiles = 1;                      // tiles per counting workgroup
 
 inline size_t tok_align(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -43,22 +46,26 @@ struct TokText {
 };
 
 // Bit 7 of each byte of the result is set iff that byte of x is an ASCII
-// letter.  x | 0x20 maps A-Z onto a-z (and nothing else onto a-z); with the
-// top bit cleared, adding 0x1F to a byte sets its bit 7 iff it is at least
-// 0x61 ('a'), adding 0x05 iff it is at least 0x7B (past 'z'), and neither
-// sum carries into the next byte.  Bytes with the top bit set are never
-// letters.
+// letter (the other bits are left as they fall).  x | 0x20 maps A-Z onto
+// a-z (and nothing else onto a-z); with the top bit cleared, adding 0x1F to
+// a byte sets its bit 7 iff it is at least 0x61 ('a'), adding 0x05 iff it is
+// at least 0x7B (past 'z'), neither sum carries into the next byte, and the
+// second implies the first, so their XOR marks a-z.  Bytes with the top bit
+// set are never letters.
 __device__ __forceinline__ uint32_t letter_bits(uint32_t x) {
     const uint32_t y = x | 0x20202020u;
     const uint32_t v = y & 0x7F7F7F7Fu;
-    return (v + 0x1F1F1F1Fu) & ~(v + 0x05050505u) & ~y & 0x80808080u;
+    return ((v + 0x1F1F1F1Fu) ^ (v + 0x05050505u)) & ~y;
 }
 
-// letter_bits result -> 4-bit mask, bit i for byte i: the four flags moved
-// to bit 0 of their bytes and multiplied so that they land, without carries,
-// in bits 28..31
-__device__ __forceinline__ uint32_t nibble_mask(uint32_t f) {
-    return (((f >> 7) & 0x01010101u) * 0x10204080u) >> 28;
+// letter_bits of two dwords a, b -> 8-bit mask, bits 0-3 for a's bytes and
+// 4-7 for b's: a's flags moved to bits 0, 8, 16, 24 and b's to 4, 12, 20,
+// 28, then one multiply by 2^24 + 2^17 + 2^10 + 2^3 carries flag i of each
+// to bit 24 + i (a) and 28 + i (b); every other product term lands, alone,
+// below bit 24 or above bit 31
+__device__ __forceinline__ uint32_t byte_mask(uint32_t fa, uint32_t fb) {
+    const uint32_t x = ((fa >> 7) & 0x01010101u) | ((fb >> 3) & 0x10101010u);
+    return (x * 0x01020408u) >> 24;
 }
 
 __device__ __forceinline__ bool is_letter(uint32_t b) { return ((b | 0x20u) - 0x61u) < 26u; }
@@ -93,8 +100,9 @@ __device__ __forceinline__ void span_masks(const TokText& t, int64_t c,
 #pragma unroll
     for (int k = 0; k < kTokLoads; ++k)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            M |= (uint64_t)nibble_mask(letter_bits(d[k][q])) << (16 * k + 4 * q);
+        for (int q = 0; q < 4; q += 2)
+            M |= (uint64_t)byte_mask(letter_bits(d[k][q]), letter_bits(d[k][q + 1]))
+                 << (16 * k + 4 * q);
     const int64_t p = c - 1;
     const uint64_t prev = (p >= t.head && p < t.N && is_letter(gp(t.base)[p])) ? 1u : 0u;
     S = M & ~((M << 1) | prev);
@@ -135,32 +143,6 @@ __device__ __forceinline__ Run<T> join(const Run<T>& a, const Run<T>& b) {
     return r;
 }
 
-// the runs of 64 text bytes from their letter mask.  Longest run: x[k] has
-// bit i set iff the 2^k bytes ending at i are letters (x[k] = x[k-1] &
-// x[k-1] << 2^(k-1)); the length is then found bit by bit from the top,
-// keeping the positions where a run of the length so far ends.
-__device__ __forceinline__ Run<uint32_t> span_run(uint64_t M) {
-    Run<uint32_t> r;
-    r.full = M == ~0ull;
-    r.pre = r.full ? 64u : (uint32_t)__builtin_ctzll(~M);
-    r.suf = r.full ? 64u : (uint32_t)__builtin_clzll(~M);
-    uint64_t x[7];
-    x[0] = M;
-#pragma unroll
-    for (int k = 1; k < 7; ++k) x[k] = x[k - 1] & (x[k - 1] << (1 << (k - 1)));
-    uint32_t L = 0;
-    uint64_t cur = ~0ull;
-#pragma unroll
-    for (int k = 6; k >= 0; --k) {
-        const uint64_t tk = cur & (L < 64 ? x[k] << L : 0ull);
-        const bool hit = tk != 0;
-        cur = hit ? tk : cur;
-        L += hit ? (1u << k) : 0u;
-    }
-    r.mx = L;
-    return r;
-}
-
 // wave-wide join in lane order; lane 0 ends with the wave's runs
 template <typename T>
 __device__ __forceinline__ Run<T> wave_join(Run<T> r, int lane) {
@@ -176,75 +158,97 @@ __device__ __forceinline__ Run<T> wave_join(Run<T> r, int lane) {
     return r;
 }
 
-// the same for the runs of 64-byte spans: every length within a wave is at
-// most 4096, so (pre, suf) and (mx, full) travel as two 32-bit values
-__device__ __forceinline__ Run<uint32_t> wave_join_spans(Run<uint32_t> r, int lane) {
+// wave-wide min and max
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t ps = __shfl_down(r.pre | (r.suf << 16), d, kWave);
-        const uint32_t mf = __shfl_down(r.mx | (r.full ? 0x10000u : 0u), d, kWave);
-        const Run<uint32_t> o{ps & 0xFFFFu, ps >> 16, mf & 0xFFFFu, (mf >> 16) != 0};
-        if ((lane & (2 * d - 1)) == 0) r = join(r, o);
+    for (int d = 32; d > 0; d >>= 1) {
+        const uint32_t o = __shfl_xor(v, d, kWave);
+        v = o < v ? o : v;
     }
-    return r;
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const uint32_t o = __shfl_xor(v, d, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
 }
 
-// a tile's runs packed into 64 bits: pre, suf, mx (each <= 16384) and full
-__device__ __forceinline__ uint64_t pack_run(const Run<uint32_t>& r) {
-    return (uint64_t)r.pre | ((uint64_t)r.suf << 16) | ((uint64_t)r.mx << 32) |
-           ((uint64_t)(r.full ? 1 : 0) << 48);
-}
-__device__ __forceinline__ Run<int64_t> unpack_run(uint64_t v) {
-    Run<int64_t> r;
-    r.pre = (int64_t)(v & 0xFFFFu);
-    r.suf = (int64_t)((v >> 16) & 0xFFFFu);
-    r.mx = (int64_t)((v >> 32) & 0xFFFFu);
-    r.full = ((v >> 48) & 1u) != 0;
-    return r;
-}
-
-// tile_counts[i] = packed counts of tile i; tile_runs[i] = its packed runs
-__global__ __launch_bounds__(kTokThreads) void k_tok_count(TokText t,
+// tile_counts[i] = packed counts of tile i; tile_ends[i] = (letters of the
+// tile after its last word start << 16) | letters before its first one
+// (both 0 when the tile has no word start).  Loads past the last tile read
+// nothing (positions beyond the text).
+__global__ __launch_bounds__(kTokThreads) void k_tok_count(TokText t, int64_t ntiles,
                                                            uint32_t* __restrict__ tile_counts,
-                                                           uint64_t* __restrict__ tile_runs) {
-    __shared__ uint32_t wsum[kTokWaves];
-    __shared__ uint32_t wrun[kTokWaves][4];
+                                                           uint32_t* __restrict__ tile_ends) {
+    __shared__ uint32_t wsum[kTokWaves], wfirst[kTokWaves], wlast[kTokWaves];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t tile = blockIdx.x;
-    const int64_t c = tile * kTokTile + (int64_t)tid * kTokSpan;
-    uint32_t d[kTokLoads][4];
-    load_span(t, c, d);
-    uint64_t M, S;
-    span_masks(t, c, d, M, S);
-    const uint32_t incl = wave_incl_scan(packed_counts(M, S), lane);
-    const Run<uint32_t> r = wave_join_spans(span_run(M), lane);
-    if (lane == 63) wsum[wv] = incl;
-    if (lane == 0) {
-        wrun[wv][0] = r.pre;
-        wrun[wv][1] = r.suf;
-        wrun[wv][2] = r.mx;
-        wrun[wv][3] = r.full ? 1u : 0u;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t s = 0;
-        Run<uint32_t> acc{0, 0, 0, true};                      // the empty stretch
+    // kTokCountTiles consecutive tiles per workgroup, all loads issued first
+    uint32_t d[kTokCountTiles][kTokLoads][4];
+#pragma unroll
+    for (int q = 0; q < kTokCountTiles; ++q)
+        load_span(t, ((int64_t)blockIdx.x * kTokCountTiles + q) * kTokTile + (int64_t)tid * kTokSpan,
+                  d[q]);
+#pragma unroll
+    for (int q = 0; q < kTokCountTiles; ++q) {
+        const int64_t tile = (int64_t)blockIdx.x * kTokCountTiles + q;
+        if (tile >= ntiles) break;                     // uniform
+        const int64_t c = tile * kTokTile + (int64_t)tid * kTokSpan;
+        uint64_t M, S;
+        span_masks(t, c, d[q], M, S);
+        const uint32_t v = packed_counts(M, S);
+        const uint32_t incl = wave_incl_scan(v, lane);
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint32_t ll = (incl - v) & 0xFFFFu, total = 0;    // letters of the tile before this thread
 #pragma unroll
         for (int w = 0; w < kTokWaves; ++w) {
-            s += wsum[w];
-            acc = join(acc, Run<uint32_t>{wrun[w][0], wrun[w][1], wrun[w][2], wrun[w][3] != 0});
+            ll += w < wv ? (wsum[w] & 0xFFFFu) : 0u;
+            total += wsum[w];
         }
-        gp(tile_counts)[tile] = s;
-        gp(tile_runs)[tile] = pack_run(acc);
+        // letter ranks of this thread's first and last word start
+        uint32_t first = 0xFFFFFFFFu, last = 0;
+        if (S) {
+            first = ll + (uint32_t)__popcll(M & ((1ull << __builtin_ctzll(S)) - 1ull));
+            last = ll + (uint32_t)__popcll(M & ((1ull << (63 - __builtin_clzll(S))) - 1ull));
+        }
+        first = wave_min(first);
+        last = wave_max(last);
+        if (lane == 0) {
+            wfirst[wv] = first;
+            wlast[wv] = last;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t f = 0xFFFFFFFFu, l = 0;
+#pragma unroll
+            for (int w = 0; w < kTokWaves; ++w) {
+                f = wfirst[w] < f ? wfirst[w] : f;
+                l = wlast[w] > l ? wlast[w] : l;
+            }
+            const uint32_t nl = total & 0xFFFFu;
+            const bool any = (total >> 16) != 0;
+            gp(tile_counts)[tile] = total;
+            gp(tile_ends)[tile] = any ? ((nl - l) << 16) | f : 0u;
+        }
+        __syncthreads();                               // wsum, wfirst, wlast reused
     }
 }
 
-// Exclusive prefix of (letters, words) over the tiles and the runs of all
-// tiles joined: each thread takes a contiguous stretch of tiles, one block
-// scan (and join) across threads, then each thread writes its stretch's
-// prefixes.  tile_base[2i] = letters before tile i, [2i+1] = words before it.
+// Exclusive prefix of (letters, words) over the tiles: each thread takes a
+// contiguous stretch of tiles, one block scan across threads, then each
+// thread writes its stretch's prefixes.  tile_base[2i] = letters before
+// tile i, [2i+1] = words before it.
+//
+// Words that reach past a tile's end, as runs joined in text order: a tile
+// with word starts is the run (letters before its first start, letters from
+// its last start on), one without is all continuation (pre = suf = its
+// letters, full), so the join of a tile's suf with the following pre is the
+// length of the word crossing there; the text's last word is the suf of all.
 __global__ __launch_bounds__(kTokScanThreads) void k_tok_scan(
-    const uint32_t* __restrict__ tile_counts, const uint64_t* __restrict__ tile_runs,
+    const uint32_t* __restrict__ tile_counts, const uint32_t* __restrict__ tile_ends,
     int64_t ntiles, int64_t* __restrict__ tile_base, int64_t* __restrict__ offsets,
     int64_t cap_words, int64_t* __restrict__ result) {
     constexpr int NW = kTokScanThreads / kWave;
@@ -256,15 +260,18 @@ __global__ __launch_bounds__(kTokScanThreads) void k_tok_scan(
     const int64_t a = (int64_t)tid * per;
     const int64_t b = a + per < ntiles ? a + per : ntiles;
     const gptr<const uint32_t> tc = gp(tile_counts);
-    const gptr<const uint64_t> tr = gp(tile_runs);
+    const gptr<const uint32_t> te = gp(tile_ends);
     int64_t sl = 0, sw = 0;
     Run<int64_t> run{0, 0, 0, true};
 #pragma unroll 8
     for (int64_t i = a; i < b; ++i) {
-        const uint32_t v = tc[i];
-        sl += v & 0xFFFFu;
+        const uint32_t v = tc[i], e = te[i];
+        const int64_t nl = v & 0xFFFFu;
+        sl += nl;
         sw += v >> 16;
-        run = join(run, unpack_run(tr[i]));
+        const bool any = (v >> 16) != 0;
+        run = join(run, Run<int64_t>{any ? (int64_t)(e & 0xFFFFu) : nl,
+                                     any ? (int64_t)(e >> 16) : nl, 0, !any});
     }
     const int64_t il = wave_incl_scan(sl, lane), iw = wave_incl_scan(sw, lane);
     run = wave_join(run, lane);
@@ -304,7 +311,7 @@ __global__ __launch_bounds__(kTokScanThreads) void k_tok_scan(
         const gptr<int64_t> r = gp(result);
         r[0] = tw;
         r[1] = tl;
-        r[2] = all.mx;
+        r[2] = all.mx > all.suf ? all.mx : all.suf;
         r[3] = tw > cap_words ? BSORT_E_CAPACITY : BSORT_OK;
         if (tw <= cap_words) gp(offsets)[tw] = tl;
     }
@@ -314,12 +321,16 @@ __global__ __launch_bounds__(kTokThreads) void k_tok_write(TokText t,
                                                            const int64_t* __restrict__ tile_base,
                                                            uint8_t* __restrict__ out,
                                                            int64_t* __restrict__ offsets,
-                                                           int64_t cap_words) {
+                                                           int64_t cap_words,
+                                                           int64_t* __restrict__ result) {
     // the tile's letters, placed at (global letter address mod 4) + rank so
     // that aligned global dwords are aligned LDS dwords, and its word starts
     // as letter ranks within the tile, both stored out in order at the end
-    __shared__ uint32_t stage32[kTokTile / 4 + 2];
-    __shared__ uint32_t wstart[kTokTile / 2];
+    // (+ one dword per lane past the end: every byte of a span is stored,
+    // non-letters to their lane's spare dword, so the staging has no branch)
+    __shared__ uint32_t stage32[kTokTile / 4 + 2 + kWave];
+    __shared__ uint16_t wstart[kTokTile / 2];
+    __shared__ uint32_t wmax[kTokWaves];
     __shared__ uint32_t wsum[kTokWaves];
     uint8_t* stage = (uint8_t*)stage32;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -345,19 +356,21 @@ __global__ __launch_bounds__(kTokThreads) void k_tok_write(TokText t,
     const int ll = (int)(before & 0xFFFFu);           // letters of the tile before this thread
     // letters, compacted in order into LDS
     int pos = skew + ll;
+    const int spare = 4 * (kTokTile / 4 + 2 + lane);
 #pragma unroll
     for (int k = 0; k < kTokLoads; ++k)
 #pragma unroll
         for (int j = 0; j < kTokBytes; ++j) {
-            if ((M >> (kTokBytes * k + j)) & 1u)
-                stage[pos++] = (uint8_t)(d[k][j >> 2] >> (8 * (j & 3)));
+            const int bit = (int)((M >> (kTokBytes * k + j)) & 1u);
+            stage[bit ? pos : spare] = (uint8_t)(d[k][j >> 2] >> (8 * (j & 3)));
+            pos += bit;
         }
     // word starts: letter rank of each one's first letter
     uint64_t sm = S;
     int w = (int)(before >> 16);                      // word starts of the tile before it
     while (sm) {
         const int j = __builtin_ctzll(sm);
-        wstart[w++] = (uint32_t)(ll + __popcll(M & ((1ull << j) - 1ull)));
+        wstart[w++] = (uint16_t)(ll + __popcll(M & ((1ull << j) - 1ull)));
         sm &= sm - 1ull;
     }
     __syncthreads();
@@ -365,8 +378,17 @@ __global__ __launch_bounds__(kTokThreads) void k_tok_write(TokText t,
     const int nw = (int)(total >> 16);
     const gptr<int64_t> off = gp(offsets) + wb;
     const int64_t room = cap_words - wb;
-    for (int i = tid; i < nw; i += kTokThreads)
-        if (i < room) off[i] = lb + (int64_t)wstart[i];
+    uint32_t inner = 0;                                // longest word inside the tile
+    for (int i = tid; i < nw; i += kTokThreads) {
+        const uint32_t a = wstart[i];
+        if (i < room) off[i] = lb + (int64_t)a;
+        if (i + 1 < nw) {
+            const uint32_t len = (uint32_t)wstart[i + 1] - a;
+            inner = len > inner ? len : inner;
+        }
+    }
+    inner = wave_max(inner);
+    if (lane == 0) wmax[wv] = inner;
     // letters [lb, lb + nl): the partial dwords at both ends byte by byte,
     // the rest as aligned dwords
     const int nl = (int)(total & 0xFFFFu);
@@ -379,6 +401,17 @@ __global__ __launch_bounds__(kTokThreads) void k_tok_write(TokText t,
     for (int i = tid; i < body; i += kTokThreads) o32[i] = stage32[s32 + i];
     const int tail0 = first + 4 * body;
     if (tid < nl - tail0 && tail0 + tid >= first) o[tail0 + tid] = stage[skew + tail0 + tid];
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int w = 0; w < kTokWaves; ++w) m = wmax[w] > m ? wmax[w] : m;
+        // one address for every tile: look first, so that the atomic (which
+        // serialises) only runs when this tile raises the maximum
+        const gptr<int64_t> r2 = gp(result) + 2;
+        if ((int64_t)m > __hip_atomic_load(r2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            __hip_atomic_fetch_max(r2, (int64_t)m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 int64_t tok_tiles(int64_t logical_bytes) { return (logical_bytes + kTokTile - 1) / kTokTile; }
@@ -387,7 +420,7 @@ int64_t tok_tiles(int64_t logical_bytes) { return (logical_bytes + kTokTile - 1)
 
 size_t tok_workspace_bytes(int64_t n_bytes) {
     const int64_t nt = tok_tiles(n_bytes + 15);
-    return tok_align(sizeof(uint32_t) * (size_t)nt) + tok_align(sizeof(uint64_t) * (size_t)nt) +
+    return 2 * tok_align(sizeof(uint32_t) * (size_t)nt) +
            tok_align(2 * sizeof(int64_t) * (size_t)nt) + 256;
 }
 
@@ -402,12 +435,15 @@ hipError_t launch_tokenize(const uint8_t* text, int64_t n_bytes, uint8_t* out, i
     char* w = (char*)ws;
     uint32_t* tc = (uint32_t*)w;
     w += tok_align(sizeof(uint32_t) * (size_t)nt);
-    uint64_t* tr = (uint64_t*)w;
-    w += tok_align(sizeof(uint64_t) * (size_t)nt);
+    uint32_t* te = (uint32_t*)w;
+    w += tok_align(sizeof(uint32_t) * (size_t)nt);
     int64_t* tb = (int64_t*)w;
-    if (nt > 0) k_tok_count<<<(unsigned)nt, kTokThreads, 0, s>>>(t, tc, tr);
-    k_tok_scan<<<1, kTokScanThreads, 0, s>>>(tc, tr, nt, tb, offsets, cap_words, result);
-    if (nt > 0) k_tok_write<<<(unsigned)nt, kTokThreads, 0, s>>>(t, tb, out, offsets, cap_words);
+    if (nt > 0)
+        k_tok_count<<<(unsigned)((nt + kTokCountTiles - 1) / kTokCountTiles), kTokThreads, 0, s>>>(
+            t, nt, tc, te);
+    k_tok_scan<<<1, kTokScanThreads, 0, s>>>(tc, te, nt, tb, offsets, cap_words, result);
+    if (nt > 0)
+        k_tok_write<<<(unsigned)nt, kTokThreads, 0, s>>>(t, tb, out, offsets, cap_words, result);
     return hipGetLastError();
 }
 
