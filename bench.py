@@ -263,6 +263,91 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
 
 
+CU_COUNTS = (8, 16, 32, 64, 128, 256)
+
+
+def cu_child(args):
+    """Child of the compute-unit scaling leg.  HSA_CU_MASK, set by the parent,
+    limits this process's kernels to part of the GPU; time the serial-stage
+    sort of the saved batch and print one JSON line."""
+    import hashlib
+    d = args.cu_data
+    bytes_ = np.load(os.path.join(d, "bytes.npy"))
+    offsets = np.load(os.path.join(d, "offsets.npy"))
+    req = np.load(os.path.join(d, "req_start.npy"))
+    import torch
+    import paper_1407_6603_amd as bs
+    from paper_1407_6603_amd import autotune
+    tile, hbm = args.tile, args.hbm_tile
+    if tile == 0 and hbm == 0:
+        tile, hbm, _ = autotune.lookup(torch.cuda.get_device_name(0), "batch4096",
+                                       args.tune_cache or autotune.CACHE)
+    dev = torch.device("cuda:0")
+    total, R, max_len = int(req[-1]), len(req) - 1, 12
+    b_t, o_t = bs.to_device(bytes_, offsets, dev)
+    rs_t = torch.from_numpy(req).to(dev)
+    ws = bs.Workspace(bs.workspace_bytes(total, max_len, R), dev)
+    perm = torch.empty(total, dtype=torch.int32, device=dev)
+    tune = bs.tuning(tile, 0, bs.FLAG_SERIAL_STAGES, hbm)
+    timer = bs.StageTimer(max_len)
+    bs.sort_batch_staged(b_t, o_t, rs_t, req, max_len, timer, tune, ws, out=perm)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        bs.sort_batch_staged(b_t, o_t, rs_t, req, max_len, timer, tune, ws, out=perm)
+    e1.record()
+    torch.cuda.synchronize()
+    bs.check_device_status(ws)
+    print(json.dumps({"ms": e0.elapsed_time(e1) / reps, "stage_ms": timer.ms(),
+                      "perm_sha": hashlib.sha256(perm.cpu().numpy().tobytes()).hexdigest()[:16]}),
+          flush=True)
+
+
+def cu_scaling_run(batch, args):
+    """The sort with every stage in order on 8, 16, ... 256 compute units:
+    one child process per count, its kernels limited by HSA_CU_MASK (CU ids
+    0..n-1), the GPU counterpart of the paper's runs with 1, 2, 4, ...
+    threads.  Runs before this process opens the GPU."""
+    import shutil
+    import subprocess
+    import tempfile
+    base = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    d = tempfile.mkdtemp(prefix="bsort_cu_", dir=base)
+    try:
+        np.save(os.path.join(d, "bytes.npy"), batch.bytes)
+        np.save(os.path.join(d, "offsets.npy"), batch.offsets)
+        np.save(os.path.join(d, "req_start.npy"), batch.req_start)
+        rows = []
+        for n in CU_COUNTS:
+            env = dict(os.environ)
+            env["HSA_CU_MASK"] = f"0:0-{n - 1}"
+            cmd = [sys.executable, os.path.abspath(__file__), "--cu-child", "--cu-data", d,
+                   "--tile", str(args.tile), "--hbm-tile", str(args.hbm_tile)]
+            if args.tune_cache:
+                cmd += ["--tune-cache", args.tune_cache]
+            res = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=300)
+            print(f"cu scaling: {n} CUs, exit {res.returncode}", file=sys.stderr, flush=True)
+            if res.returncode != 0:
+                return {"error": f"{n} CUs: exit {res.returncode}: {res.stderr[-600:]}"}
+            row = json.loads(res.stdout.strip().splitlines()[-1])
+            st = row["stage_ms"]
+            big = max((k for k in st if k.startswith(("lds_", "tiles_"))), key=st.get)
+            row.update({"cus": n, "hsa_cu_mask": env["HSA_CU_MASK"],
+                        "words_per_s": batch.total / (row["ms"] / 1e3),
+                        "longest_stage": big, "longest_stage_ms": st[big]})
+            rows.append(row)
+        for r in rows:
+            r["speedup"] = rows[0]["ms"] / r["ms"]
+            r["efficiency"] = r["speedup"] * rows[0]["cus"] / r["cus"]
+        return {"stages": "all in order on one stream (FLAG_SERIAL_STAGES)",
+                "limit": "HSA_CU_MASK per child process", "rows": rows}
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,6 +361,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-cu-scaling", action="store_true",
+                    help="skip the sort on 8, 16, ... 256 compute units (child processes)")
+    ap.add_argument("--cu-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cu-data", default="", help=argparse.SUPPRESS)
     ap.add_argument("--no-tokenize", action="store_true",
                     help="skip the raw-text pre-processing leg")
     ap.add_argument("--no-serial", action="store_true",
@@ -304,6 +393,9 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.cu_child:
+        cu_child(args)
+        return
 
     # inputs first (spawned worker processes, before the GPU is opened)
     t0 = time.time()
@@ -318,6 +410,8 @@ def main():
     if not args.no_tokenize:
         text = wordgen.raw_text(wordgen.Words(batch.bytes, batch.offsets), seed=4)
     gen_s = time.time() - t0
+    # child processes first: this process must not have opened the GPU yet
+    cu_scaling = None if args.no_cu_scaling else cu_scaling_run(batch, args)
     max_len = 12
     total = batch.total
 
@@ -375,6 +469,10 @@ def main():
     value = total / (ms_per_step / 1e3)
     bs.check_device_status(ws)
     got = perm.cpu().numpy()
+    if cu_scaling is not None and "rows" in cu_scaling:
+        import hashlib
+        sha = hashlib.sha256(got.tobytes()).hexdigest()[:16]
+        cu_scaling["identical"] = all(r["perm_sha"] == sha for r in cu_scaling["rows"])
 
     # ---- per-stage times with each stage alone on the GPU (every stage in
     # order on one stream); the timed region above runs them side by side
@@ -566,6 +664,7 @@ def main():
         "stage_ms": stage_ms,
         "serial_stages": serial,
         "tokenize": tok,
+        "cu_scaling": cu_scaling,
         "merge_phases_max": phases_max,
         "work": struct,
         "roofline": roof,

@@ -551,8 +551,11 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     if ((e = launch_sort_prep(J, b, s)) != hipSuccess) return e;
     if ((e = rec(1, 1, s)) != hipSuccess) return e;
 
+    // BSORT_FLAG_SERIAL_STAGES: every stage on s, no library stream, no
+    // read-back (the merge-split launches its phase bound)
+    const bool fan = !(b.flags & BSORT_FLAG_SERIAL_STAGES);
     bool readback = false;
-    if (d_pmax && b.phase_bound > 4 && !(b.flags & kFlagTilesOnly)) {
+    if (fan && d_pmax && b.phase_bound > 4 && !(b.flags & kFlagTilesOnly)) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return e;
         readback = cs == hipStreamCaptureStatusNone;
@@ -560,16 +563,18 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    FanPool& f = g_fan[dev][fan_pool_for(dev, s)];
-    std::lock_guard<std::mutex> lock(f.mu);
-    if ((e = fan_init(f)) != hipSuccess) return e;
+    FanPool& f = g_fan[dev][fan ? fan_pool_for(dev, s) : 0];
+    std::unique_lock<std::mutex> lock(f.mu, std::defer_lock);
+    if (fan) {
+        lock.lock();
+        if ((e = fan_init(f)) != hipSuccess) return e;
+    }
     if (readback) {
         if ((e = hipMemcpyAsync(f.host_pmax, d_pmax, sizeof(int32_t), hipMemcpyDeviceToHost,
                                 s)) != hipSuccess)
             return e;
         if ((e = hipEventRecord(f.pmax_ev, s)) != hipSuccess) return e;
     }
-    const bool fan = !(b.flags & BSORT_FLAG_SERIAL_STAGES);
     hipStream_t st[kFan] = {s, f.aux[0], f.aux[1], f.aux[2]};
     if (fan) {
         if ((e = hipEventRecord(f.fork, s)) != hipSuccess) return e;

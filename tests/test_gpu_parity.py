@@ -415,3 +415,4 @@ def test_staged_batch_equals_unstaged(bs, ws, batch_small):
     assert list(ms) == bs.stage_names(12)
     assert all(v >= 0 for v in ms.values())
     assert np.array_equal(perm.cpu().numpy(), gpu_batch(bs, ws, sub, 12))
+
