@@ -37,17 +37,26 @@ PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 128 B/clk/CU LDS bandwidth: 78.6
 # profiles/batch4096_hbm_traffic.md (scaled by the plain-copy calibration
 # there), with a digest of the kernel sources they were taken on: a kernel
 # changed since then reports no traffic.
-KERNEL_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
+SORT_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
+TOK_SOURCES = ("paper_1407_6603_amd/csrc/k_tokenize.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TRAFFIC = {
-    "k_bucket_lds<2, 1024, 8192>": {"read": 80752723, "write": 61130048,
-                                    "sources": "9009dafa700b20b8"},
+    "k_bucket_lds<2, 1024, 16384>": {"read": 66615591, "write": 22064384,
+                                     "files": SORT_SOURCES, "sources": "a2ddf5039f339c12"},
+    "k_bucket_lds<3, 1024, 8192>": {"read": 38453402, "write": 12693760,
+                                    "files": SORT_SOURCES, "sources": "a2ddf5039f339c12"},
+    "k_tok_count": {"read": 189689291, "write": 749648,
+                    "files": TOK_SOURCES, "sources": "365517177ff34074"},
+    "k_tok_scan": {"read": 110202, "write": 183712,
+                   "files": TOK_SOURCES, "sources": "365517177ff34074"},
+    "k_tok_write": {"read": 191124352, "write": 403948624,
+                    "files": TOK_SOURCES, "sources": "365517177ff34074"},
 }
 
 
-def sources_digest():
+def sources_digest(files):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -55,7 +64,7 @@ def sources_digest():
 
 def measured_traffic(kernel):
     t = TRAFFIC.get(kernel)
-    if t is None or t["sources"] != sources_digest():
+    if t is None or t["sources"] != sources_digest(t["files"]):
         return None
     return t["read"] + t["write"]
 
@@ -563,13 +572,16 @@ def main():
         # algorithmic HBM bytes: the text read once, the letters and the
         # int64 offsets written once
         tb = len(text) + nl + 8 * (nw + 1)
+        parts = [measured_traffic(k) for k in ("k_tok_count", "k_tok_scan", "k_tok_write")]
+        tok_traffic = None if None in parts else sum(parts)
         gbs = tb / (t_ms / 1e3) / 1e9
         tok = {"text_bytes": len(text), "words": nw, "letters": nl, "max_len": ml,
                "ms": t_ms, "words_per_s": nw / (t_ms / 1e3), "text_gb_per_s": len(text) / t_ms / 1e6,
                "identical_to_batch_words": same,
                "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                             "frac": gbs / PEAK_HBM_GBS, "bytes_algorithmic": tb,
-                            "kernels": "k_tok_count, k_tok_scan, k_tok_write, k_tok_maxlen"}}
+                            "traffic": tok_traffic,
+                            "kernels": "k_tok_count, k_tok_scan, k_tok_write"}}
         del text_t, tws, words_t, offsets_t, res_t
 
     # ---- roofline of the dominant kernel (the stage with the largest time;
