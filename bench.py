@@ -374,6 +374,8 @@ def main():
                     help="skip the sort on 8, 16, ... 256 compute units (child processes)")
     ap.add_argument("--cu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cu-data", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--no-unbucketed", action="store_true",
+                    help="skip the whole-list (unbucketed) sorts")
     ap.add_argument("--no-tokenize", action="store_true",
                     help="skip the raw-text pre-processing leg")
     ap.add_argument("--no-serial", action="store_true",
@@ -584,6 +586,58 @@ def main():
                             "kernels": "k_tok_count, k_tok_scan, k_tok_write"}}
         del text_t, tws, words_t, offsets_t, res_t
 
+    # ---- unbucketed ablation (Table 1 rows 2-3): every list sorted whole by
+    # fixed-width keys (alphabetic; length only; length then bytes), the same
+    # OETS and merge-split, no sub-arrays
+    unb = None
+    if not args.no_unbucketed:
+        lens = np.diff(batch.offsets)
+        lid = np.repeat(np.arange(batch.R), np.diff(batch.req_start))
+        n_r = np.diff(batch.req_start).astype(np.float64)
+        cnt = np.bincount(lid * (max_len + 1) + lens, minlength=batch.R * (max_len + 1))
+        cmp_bucketed = float((cnt * (cnt - 1) / 2).sum())
+        cmp_whole = float((n_r * (n_r - 1) / 2).sum())
+        uws = bs.Workspace(device=dev)
+        legs = {}
+        for name, mode, width in (("alphabetic", bs.KEY_BYTES, max_len),
+                                  ("length", bs.KEY_LENGTH, 1),
+                                  ("length_then_bytes", bs.KEY_LENGTH_BYTES, max_len + 1)):
+            kb, ko = bs.fixed_width(b_t, o_t, width, mode)
+            uperm = torch.empty(total, dtype=torch.int32, device=dev)
+            bs.sort_batch(kb, ko, rs_t, batch.req_start, width, tune, uws, out=uperm)
+            torch.cuda.synchronize()
+            reps = 3
+            ev0.record(stream)
+            for _ in range(reps):
+                bs.sort_batch(kb, ko, rs_t, batch.req_start, width, tune, uws, out=uperm)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            bs.check_device_status(uws)
+            u_ms = ev0.elapsed_time(ev1) / reps
+            up = uperm.cpu().numpy()
+            if mode == bs.KEY_LENGTH_BYTES:
+                ok = bool(np.array_equal(up, got))
+            else:                                  # library routines on 16 sampled lists
+                ok = True
+                for r in range(0, batch.R, batch.R // 16):
+                    a, e = int(batch.req_start[r]), int(batch.req_start[r + 1])
+                    if mode == bs.KEY_LENGTH:
+                        ex = np.argsort(lens[a:e], kind="stable")
+                    else:
+                        wl = [batch.bytes[batch.offsets[i]:batch.offsets[i + 1]].tobytes()
+                              for i in range(a, e)]
+                        ex = np.array(sorted(range(e - a), key=lambda i: wl[i]))
+                    ok = ok and bool(np.array_equal(up[a:e], ex))
+            legs[name] = {"ms": u_ms, "words_per_s": total / (u_ms / 1e3), "key_bytes": width,
+                          "vs_bucketed": u_ms / ms_per_step, "checked": ok}
+            del kb, ko, uperm
+        unb = {"bucketed_ms": ms_per_step, "sorts": legs,
+               "bubble_comparisons": {"bucketed": cmp_bucketed, "whole_list": cmp_whole,
+                                      "ratio": cmp_whole / cmp_bucketed},
+               "check": "length_then_bytes against the bucketed result (all lists); the "
+                        "others against a stable library sort on 16 sampled lists"}
+        del uws
+
     # ---- roofline of the dominant kernel (the stage with the largest time;
     # every tile and in-LDS stage is exactly one kernel launch)
     struct, merge_bytes, phases_max = workload_structure(
@@ -676,6 +730,7 @@ def main():
         "stage_ms": stage_ms,
         "serial_stages": serial,
         "tokenize": tok,
+        "unbucketed": unb,
         "cu_scaling": cu_scaling,
         "merge_phases_max": phases_max,
         "work": struct,

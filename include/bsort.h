@@ -224,6 +224,35 @@ bsort_status bsort_tokenize(const uint8_t *text, int64_t n_bytes, uint8_t *words
                             size_t ws_bytes, bsort_stream_t stream);
 
 /*
+ * Unbucketed ablation (Section II, Table 1 rows 2-3: the whole file sorted
+ * by alphabetic order, or by word length, without sub-arrays).  Rewrites
+ * every word as a key of one width, so that the sorting calls see a single
+ * sub-array per list and run the same odd-even transposition sort and
+ * merge-split over the whole list:
+ *   BSORT_KEY_BYTES         the word's bytes, zero-padded to width
+ *                           (alphabetic order; width >= longest word)
+ *   BSORT_KEY_LENGTH        one byte holding the length (width 1)
+ *   BSORT_KEY_LENGTH_BYTES  the length byte, then the padded bytes (the
+ *                           bucketed sort's order; width >= 1 + longest)
+ *
+ *   bytes, offsets  the words (device, as for the other calls; words whose
+ *                   offsets leave [0, n_bytes] are not read and set status)
+ *   out             device [n_words * width]
+ *   offsets_out     device [n_words + 1]: i * width
+ *   status          device int32: 0, or nonzero if a word did not fit the
+ *                   width (or is longer than 255 bytes with a length byte);
+ *                   written by the call's stream work
+ * Sorting (out, offsets_out) with max_len = width gives, per list, the
+ * stable order of those keys.
+ */
+#define BSORT_KEY_BYTES 0
+#define BSORT_KEY_LENGTH 1
+#define BSORT_KEY_LENGTH_BYTES 2
+bsort_status bsort_fixed_width(const uint8_t *bytes, int64_t n_bytes, const int64_t *offsets,
+                               int64_t n_words, int32_t width, int32_t mode, uint8_t *out,
+                               int64_t *offsets_out, int32_t *status, bsort_stream_t stream);
+
+/*
  * A captured batch: bsort_sort_batch's launches recorded once into a HIP
  * graph for batches within the given capacity, then replayed by
  * bsort_plan_execute with one graph launch (plus one small launch that

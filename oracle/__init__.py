@@ -19,6 +19,9 @@ Contents
   sub-array contents (the paper's count array and sub-array fill).
 * ``pack_keys`` -- fixed-width big-endian uint64 key lanes of equal-length
   words (Section III approach two: one fixed width per sub-array).
+* ``bubble_sort_whole`` -- Section II, Table 1 rows 2-3: the whole list
+  bubble-sorted without sub-arrays, by alphabetic order, by length, or by
+  length then bytes.
 * ``tokenize`` -- Section II pre-processing phase 1: raw text to words,
   a word being a maximal run of ASCII letters (every other byte, the paper's
   "special characters" among them, separates words and is dropped).
@@ -96,9 +99,10 @@ def _load(path: str):
     L.oracle_pack_keys.argtypes = [P, P, P, i32, i32, P]
     L.oracle_max_threads.argtypes = []
     L.oracle_tokenize.argtypes = [P, i64, P, P, i64, P, P]
+    L.oracle_bubble_sort_whole.argtypes = [P, i64, P, i32, ctypes.c_int, P, P]
     for f in (L.oracle_bucketize, L.oracle_bubble_sort, L.oracle_bubble_sort_batch,
               L.oracle_definition_sort, L.oracle_definition_sort_batch, L.oracle_pack_keys,
-              L.oracle_max_threads, L.oracle_tokenize):
+              L.oracle_max_threads, L.oracle_tokenize, L.oracle_bubble_sort_whole):
         f.restype = ctypes.c_int
     return L
 
@@ -129,6 +133,23 @@ def _check(rc: int, what: str):
 
 def default_max_len(offsets: np.ndarray) -> int:
     return int(np.diff(offsets).max()) if len(offsets) > 1 else 0
+
+
+WHOLE_ALPHABETIC, WHOLE_LENGTH, WHOLE_LENGTH_BYTES = 0, 1, 2
+
+
+def bubble_sort_whole(bytes_, offsets, key: int) -> Tuple[np.ndarray, int]:
+    """Section II, Table 1 rows 2-3: one bubble sort over the whole list, no
+    sub-arrays, by alphabetic order (WHOLE_ALPHABETIC), by length
+    (WHOLE_LENGTH) or by length then bytes (WHOLE_LENGTH_BYTES).  Returns
+    (perm, comparisons).  O(n^2): small lists only."""
+    b, o, nb = _prep(bytes_, offsets)
+    n = len(o) - 1
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    cmp = ctypes.c_int64(0)
+    _check(lib().oracle_bubble_sort_whole(_ptr(b), nb, _ptr(o), n, key, _ptr(perm),
+                                          ctypes.byref(cmp)), "bubble_sort_whole")
+    return perm[:n], cmp.value
 
 
 def tokenize(text) -> Tuple[np.ndarray, np.ndarray]:

@@ -295,6 +295,50 @@ int oracle_pack_keys(const uint8_t *bytes, const int64_t *offsets, const int32_t
 }
 
 /*
+ * Section II, Table 1 rows 2-3: the whole file bubble-sorted without
+ * sub-arrays, by alphabetic order (key 0: bytes compared as unsigned, a
+ * word that is a prefix of another sorting first) or by word length
+ * (key 1); key 2 compares length, then bytes (the bucketed order, reached
+ * without buckets).  Bubble passes over the whole list, swapping only a
+ * strictly greater left word, so equal keys keep input order.  Returns the
+ * comparison count through *comparisons (n(n-1)/2).
+ */
+static int whole_cmp(const uint8_t *bytes, const int64_t *offsets, int32_t a, int32_t b, int key)
+{
+    const int64_t la = offsets[a + 1] - offsets[a], lb = offsets[b + 1] - offsets[b];
+    if (key == 1 || key == 2) {
+        if (la != lb) return la < lb ? -1 : 1;
+        if (key == 1) return 0;
+    }
+    const int64_t m = la < lb ? la : lb;
+    const int r = memcmp(bytes + offsets[a], bytes + offsets[b], (size_t)m);
+    if (r != 0) return r;
+    return la < lb ? -1 : (la > lb ? 1 : 0);
+}
+
+int oracle_bubble_sort_whole(const uint8_t *bytes, int64_t n_bytes, const int64_t *offsets,
+                             int32_t n, int key, int32_t *perm, int64_t *comparisons)
+{
+    if (n < 0 || key < 0 || key > 2) return ORACLE_E_INVALID;
+    for (int32_t i = 0; i < n; ++i)
+        if (offsets[i] < 0 || offsets[i + 1] < offsets[i] || offsets[i + 1] > n_bytes)
+            return ORACLE_E_INVALID;
+    for (int32_t i = 0; i < n; ++i) perm[i] = i;
+    int64_t cmp = 0;
+    for (int32_t pass = 0; pass + 1 < n; ++pass)
+        for (int32_t j = 0; j + 1 < n - pass; ++j) {
+            ++cmp;
+            if (whole_cmp(bytes, offsets, perm[j], perm[j + 1], key) > 0) {
+                const int32_t t = perm[j];
+                perm[j] = perm[j + 1];
+                perm[j + 1] = t;
+            }
+        }
+    *comparisons = cmp;
+    return ORACLE_OK;
+}
+
+/*
  * Section II pre-processing phase 1 (Section III approach one step 2): the
  * special characters are removed and the text is split into words.  Reading
  * where the paper only gives examples (quote, comma, full stop, question and

@@ -170,6 +170,31 @@ def tokenize(text_t: torch.Tensor, ws: Optional[Workspace] = None, cap_words: Op
     return words[:nl], offsets[:nw + 1], ml
 
 
+KEY_BYTES, KEY_LENGTH, KEY_LENGTH_BYTES = _lib.KEY_BYTES, _lib.KEY_LENGTH, _lib.KEY_LENGTH_BYTES
+
+
+def fixed_width(bytes_t: torch.Tensor, offsets_t: torch.Tensor, width: int, mode: int,
+                stream=None, check: bool = True):
+    """Every word as a key of one width (the unbucketed ablation): returns
+    (bytes_t, offsets_t) of n words of `width` bytes each.  mode: KEY_BYTES,
+    KEY_LENGTH or KEY_LENGTH_BYTES.  With check, waits and raises if a word
+    did not fit."""
+    _require_gpu()
+    _check_words(bytes_t, offsets_t)
+    n = offsets_t.numel() - 1
+    dev = offsets_t.device
+    out = torch.empty(max(n * width, 1), dtype=torch.uint8, device=dev)
+    offs = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    _lib.check(_lib.load().bsort_fixed_width(_ptr(bytes_t), bytes_t.numel(), _ptr(offsets_t), n,
+                                             width, mode,
+                                             _ptr(out), _ptr(offs), _ptr(status),
+                                             _stream(stream)))
+    if check and int(status.cpu()) != 0:
+        raise _lib.BsortError(2, f"a word does not fit a {width}-byte key")
+    return out[:n * width], offs
+
+
 def sort_text(text_t: torch.Tensor, tune: Optional[Tuning] = None,
               ws: Optional[Workspace] = None, stream=None):
     """The paper's three phases on raw text: tokenize, then sort the words

@@ -267,6 +267,23 @@ size_t bsort_workspace_bytes(int64_t total_words, int32_t max_len, int32_t n_req
     return L.bytes;
 }
 
+bsort_status bsort_fixed_width(const uint8_t* bytes, int64_t n_bytes, const int64_t* offsets,
+                               int64_t n_words,
+                               int32_t width, int32_t mode, uint8_t* out, int64_t* offsets_out,
+                               int32_t* status, bsort_stream_t stream) {
+    if (n_words < 0 || n_bytes < 0 || width < 1) return fail(BSORT_E_INVALID, "bad size");
+    if (mode != BSORT_KEY_BYTES && mode != BSORT_KEY_LENGTH && mode != BSORT_KEY_LENGTH_BYTES)
+        return fail(BSORT_E_INVALID, "unknown key mode");
+    if (mode == BSORT_KEY_LENGTH && width != 1)
+        return fail(BSORT_E_INVALID, "a length key is one byte wide");
+    if (width > BSORT_MAX_LEN) return fail(BSORT_E_TOO_LONG, "width > BSORT_MAX_LEN");
+    if (!offsets || !offsets_out || !status) return fail(BSORT_E_INVALID, "NULL pointer");
+    if (n_words > 0 && (!bytes || !out)) return fail(BSORT_E_INVALID, "NULL pointer");
+    HIP_TRY(launch_fixed_width(bytes, n_bytes, offsets, n_words, width, mode, out, offsets_out,
+                               status, (hipStream_t)stream));
+    return BSORT_OK;
+}
+
 size_t bsort_tokenize_workspace_bytes(int64_t n_bytes) {
     return n_bytes < 0 ? 0 : tok_workspace_bytes(n_bytes);
 }

@@ -377,6 +377,12 @@ hipError_t launch_merge_pairs(const Job* J, const Bounds& b, int phase, hipStrea
 // dynamic LDS the batched pair merge needs for records up to dmax dwords
 int pair_merge_lds(int dmax);
 
+// fixed-width keys for the unbucketed ablation (k_fixed_width.hip)
+hipError_t launch_fixed_width(const uint8_t* bytes, int64_t n_bytes, const int64_t* offsets,
+                              int64_t n_words,
+                              int32_t width, int32_t mode, uint8_t* out, int64_t* offsets_out,
+                              int32_t* status, hipStream_t s);
+
 // pre-processing, raw text to words (k_tokenize.hip)
 size_t tok_workspace_bytes(int64_t n_bytes);
 hipError_t launch_tokenize(const uint8_t* text, int64_t n_bytes, uint8_t* out, int64_t* offsets,

@@ -189,8 +189,34 @@ def pin_tokenize(oracle):
     return None
 
 
+def pin_whole_sorts(oracle):
+    """Whole-list bubble sorts (Table 1 rows 2-3): alphabetic order equals
+    Python's stable sort on the words (bytes compare unsigned, a prefix
+    first); length order equals numpy's stable argsort of the lengths;
+    length-then-bytes equals the definition; n(n-1)/2 comparisons."""
+    rng = np.random.default_rng(29)
+    cases = [wordgen.random_words(rng, n, 0, 6, alphabet=b"abAB\x00\xff") for n in (0, 1, 2, 7, 60)]
+    cases += [wordgen.random_words(rng, 300, 1, 9), wordgen.single(1)]
+    for w in cases:
+        wl = w.as_list()
+        n = len(wl)
+        a, ca = oracle.bubble_sort_whole(w.bytes, w.offsets, oracle.WHOLE_ALPHABETIC)
+        if a.tolist() != sorted(range(n), key=lambda i: wl[i]):
+            return f"alphabetic whole sort differs (n={n})"
+        l, cl = oracle.bubble_sort_whole(w.bytes, w.offsets, oracle.WHOLE_LENGTH)
+        if l.tolist() != np.argsort(np.diff(w.offsets), kind="stable").tolist():
+            return f"length whole sort differs (n={n})"
+        lb, _ = oracle.bubble_sort_whole(w.bytes, w.offsets, oracle.WHOLE_LENGTH_BYTES)
+        if lb.tolist() != oracle.definition_sort(w.bytes, w.offsets).tolist():
+            return f"length-then-bytes whole sort differs (n={n})"
+        if ca != n * (n - 1) // 2 or cl != ca:
+            return f"comparisons {ca} != {n * (n - 1) // 2}"
+    return None
+
+
 ALL_PINS = [pin_golden, pin_brute_force, pin_library_sort, pin_bucketize_closed_form,
-            pin_comparison_count, pin_pack_closed_form, pin_batch_matches_single, pin_tokenize]
+            pin_comparison_count, pin_pack_closed_form, pin_batch_matches_single, pin_tokenize,
+            pin_whole_sorts]
 
 
 def run_all(oracle):

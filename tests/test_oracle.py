@@ -125,6 +125,8 @@ MUTANTS = {
                                     "return (c >= 'A' && c <= 'Z') || (c >= 'a' && c <= 'z') "
                                     "|| c >= 0x80;"),
     "tokenize_no_split": ("            in_word = 0;\n", "            ;\n"),
+    "whole_prefix_last": ("    return la < lb ? -1 : (la > lb ? 1 : 0);\n}\n\nint oracle_bubble_sort_whole",
+                          "    return la < lb ? 1 : (la > lb ? -1 : 0);\n}\n\nint oracle_bubble_sort_whole"),
     "definition_ignores_length": ("if (la != lb) return la < lb ? -1 : 1;",
                                   "if (la != lb) { int q = memcmp(c->bytes + c->offsets[a], "
                                   "c->bytes + c->offsets[b], (size_t)(la < lb ? la : lb)); "
