@@ -374,6 +374,8 @@ def main():
                     help="skip the sort on 8, 16, ... 256 compute units (child processes)")
     ap.add_argument("--cu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cu-data", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--no-layout", action="store_true",
+                    help="skip the data-structure (packed keys vs text) comparison")
     ap.add_argument("--no-unbucketed", action="store_true",
                     help="skip the whole-list (unbucketed) sorts")
     ap.add_argument("--no-tokenize", action="store_true",
@@ -586,6 +588,47 @@ def main():
                             "kernels": "k_tok_count, k_tok_scan, k_tok_write"}}
         del text_t, tws, words_t, offsets_t, res_t
 
+    # ---- data-structure ablation (Section III, Tables 2 and 3): the medium
+    # list, each sub-array sorted whole by one workgroup, with the words as
+    # packed keys or read from the text through the offsets; the library's
+    # tiled path on the same list beside them
+    layout = None
+    if not args.no_layout:
+        w2 = wordgen.single(2)
+        ml2 = wordgen.SINGLE[2].lmax
+        lb_t, lo_t = bs.to_device(w2.bytes, w2.offsets, dev)
+        lws = bs.Workspace(device=dev)
+        counts_t, starts_t, order_t = bs.bucketize(lb_t, lo_t, ml2, ws=lws)
+        lperm = torch.empty(w2.n, dtype=torch.int32, device=dev)
+        res = {}
+        ref = None
+        for name, fn in (("packed", lambda: bs.oets_buckets(lb_t, lo_t, counts_t, starts_t,
+                                                             order_t, ml2, bs.LAYOUT_PACKED,
+                                                             out=lperm, check=False)),
+                         ("text", lambda: bs.oets_buckets(lb_t, lo_t, counts_t, starts_t,
+                                                           order_t, ml2, bs.LAYOUT_TEXT,
+                                                           out=lperm, check=False)),
+                         ("library_path", lambda: bs.sort_buckets(lb_t, lo_t, counts_t,
+                                                                   starts_t, order_t, ml2,
+                                                                   tune, lws, out=lperm))):
+            fn()
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(3):
+                fn()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            l_ms = ev0.elapsed_time(ev1) / 3
+            got2 = lperm.cpu().numpy()
+            ref = got2 if ref is None else ref
+            res[name] = {"ms": l_ms, "words_per_s": w2.n / (l_ms / 1e3),
+                         "identical": bool(np.array_equal(got2, ref))}
+        bs.check_device_status(lws)
+        layout = {"workload": f"medium list: {w2.n} words, lengths 1-{ml2}", "sorts": res,
+                  "text_over_packed": res["text"]["ms"] / res["packed"]["ms"],
+                  "packed_over_library_path": res["packed"]["ms"] / res["library_path"]["ms"]}
+        del lb_t, lo_t, lws, counts_t, starts_t, order_t, lperm
+
     # ---- unbucketed ablation (Table 1 rows 2-3): every list sorted whole by
     # fixed-width keys (alphabetic; length only; length then bytes), the same
     # OETS and merge-split, no sub-arrays
@@ -731,6 +774,7 @@ def main():
         "serial_stages": serial,
         "tokenize": tok,
         "unbucketed": unb,
+        "data_structure": layout,
         "cu_scaling": cu_scaling,
         "merge_phases_max": phases_max,
         "work": struct,

@@ -253,6 +253,27 @@ bsort_status bsort_fixed_width(const uint8_t *bytes, int64_t n_bytes, const int6
                                int64_t *offsets_out, int32_t *status, bsort_stream_t stream);
 
 /*
+ * Data-structure ablation (Section III: approach one holds the words as
+ * vectors of strings, approach two as a fixed-width character array per
+ * length; Tables 2 and 3 time the same sort on each).  Sorts every
+ * sub-array of one list made by bsort_bucketize (same w and b) with one
+ * workgroup per sub-array running odd-even transposition sort over the
+ * whole sub-array (n phases; no tiles, no merge-split), the words held as
+ *   BSORT_LAYOUT_PACKED  big-endian key dwords in LDS (a compare reads LDS)
+ *   BSORT_LAYOUT_TEXT    positions only; a compare reads both words'
+ *                        bytes from the text through order and offsets
+ * and writes the same perm as bsort_sort_buckets.  A sub-array must fit
+ * 144 KiB of LDS ((ceil(L/4) + 1) * 4 bytes per word packed, 4 text);
+ * status (device int32) is 0, or has bit 1 set if a sub-array did not fit
+ * (it is left unsorted) and bit 2 if order or offsets pointed outside the
+ * words.  Asynchronous on the stream.
+ */
+#define BSORT_LAYOUT_PACKED 0
+#define BSORT_LAYOUT_TEXT 1
+bsort_status bsort_oets_buckets(const bsort_words *w, const bsort_buckets *b, int32_t *perm,
+                                int32_t layout, int32_t *status, bsort_stream_t stream);
+
+/*
  * A captured batch: bsort_sort_batch's launches recorded once into a HIP
  * graph for batches within the given capacity, then replayed by
  * bsort_plan_execute with one graph launch (plus one small launch that

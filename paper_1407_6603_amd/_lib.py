@@ -21,6 +21,7 @@ FLAG_PER_BUCKET_LAUNCH = 1
 FLAG_TILES_ONLY = 2
 FLAG_SERIAL_STAGES = 4
 KEY_BYTES, KEY_LENGTH, KEY_LENGTH_BYTES = 0, 1, 2
+LAYOUT_PACKED, LAYOUT_TEXT = 0, 1
 
 EXPORTS = [
     "bsort_workspace_bytes", "bsort_bucketize", "bsort_sort_buckets", "bsort_sort_batch",
@@ -28,7 +29,7 @@ EXPORTS = [
     "bsort_plan_destroy", "bsort_stage_count", "bsort_stage_name", "bsort_sort_batch_staged",
     "bsort_get_device_status", "bsort_status_string",
     "bsort_last_error", "bsort_version", "bsort_tokenize_workspace_bytes", "bsort_tokenize",
-    "bsort_fixed_width",
+    "bsort_fixed_width", "bsort_oets_buckets",
 ]
 
 
@@ -101,6 +102,8 @@ def load(path: str = LIB_PATH):
     L.bsort_tokenize.restype = ctypes.c_int
     L.bsort_fixed_width.argtypes = [P, i64, P, i64, i32, i32, P, P, P, P]
     L.bsort_fixed_width.restype = ctypes.c_int
+    L.bsort_oets_buckets.argtypes = [ctypes.POINTER(Words), ctypes.POINTER(Buckets), P, i32, P, P]
+    L.bsort_oets_buckets.restype = ctypes.c_int
     for f in (L.bsort_bucketize, L.bsort_sort_buckets, L.bsort_sort_batch,
               L.bsort_plan_create, L.bsort_plan_execute, L.bsort_get_device_status):
         f.restype = ctypes.c_int

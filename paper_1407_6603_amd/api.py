@@ -195,6 +195,33 @@ def fixed_width(bytes_t: torch.Tensor, offsets_t: torch.Tensor, width: int, mode
     return out[:n * width], offs
 
 
+LAYOUT_PACKED, LAYOUT_TEXT = _lib.LAYOUT_PACKED, _lib.LAYOUT_TEXT
+
+
+def oets_buckets(bytes_t: torch.Tensor, offsets_t: torch.Tensor, counts: torch.Tensor,
+                 starts: torch.Tensor, order: torch.Tensor, max_len: int, layout: int,
+                 stream=None, out: Optional[torch.Tensor] = None, check: bool = True):
+    """Data-structure ablation: each sub-array (from bucketize) sorted whole by
+    one workgroup, the words held as packed keys (LAYOUT_PACKED) or read from
+    the text through the offsets (LAYOUT_TEXT).  Returns perm."""
+    _require_gpu()
+    _check_words(bytes_t, offsets_t)
+    n = offsets_t.numel() - 1
+    dev = offsets_t.device
+    perm = out if out is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    w = _lib.Words(_ptr(bytes_t), bytes_t.numel(), _ptr(offsets_t), n, max_len)
+    b = _lib.Buckets(_ptr(counts), _ptr(starts), _ptr(order))
+    _lib.check(_lib.load().bsort_oets_buckets(ctypes.byref(w), ctypes.byref(b), _ptr(perm),
+                                              layout, _ptr(status), _stream(stream)))
+    if check:
+        st = int(status.cpu())
+        if st:
+            raise _lib.BsortError(1, f"layout sort status {st} (1: a sub-array did not fit "
+                                     "LDS, 2: order or offsets out of range)")
+    return perm
+
+
 def sort_text(text_t: torch.Tensor, tune: Optional[Tuning] = None,
               ws: Optional[Workspace] = None, stream=None):
     """The paper's three phases on raw text: tokenize, then sort the words

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["bsort_api.hip", "k_bucketize.hip", "k_sort.hip", "k_oets.hip", "k_tokenize.hip",
-           "k_fixed_width.hip"]
+           "k_fixed_width.hip", "k_layout.hip"]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed-fp32 VALU ops (none are intended here)

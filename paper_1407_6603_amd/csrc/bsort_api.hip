@@ -284,6 +284,21 @@ bsort_status bsort_fixed_width(const uint8_t* bytes, int64_t n_bytes, const int6
     return BSORT_OK;
 }
 
+bsort_status bsort_oets_buckets(const bsort_words* w, const bsort_buckets* b, int32_t* perm,
+                                int32_t layout, int32_t* status, bsort_stream_t stream) {
+    bsort_status st = check_words(w);
+    if (st != BSORT_OK) return st;
+    if ((st = check_buckets(b, w->n_words)) != BSORT_OK) return st;
+    if (layout != BSORT_LAYOUT_PACKED && layout != BSORT_LAYOUT_TEXT)
+        return fail(BSORT_E_INVALID, "unknown layout");
+    if (!status) return fail(BSORT_E_INVALID, "status is NULL");
+    if (w->n_words > 0 && !perm) return fail(BSORT_E_INVALID, "perm is NULL");
+    HIP_TRY(launch_layout_oets(w->bytes, w->n_bytes, w->offsets, w->n_words, w->max_len,
+                               b->counts, b->starts, b->order, perm, layout, status,
+                               (hipStream_t)stream));
+    return BSORT_OK;
+}
+
 size_t bsort_tokenize_workspace_bytes(int64_t n_bytes) {
     return n_bytes < 0 ? 0 : tok_workspace_bytes(n_bytes);
 }

@@ -383,6 +383,12 @@ hipError_t launch_fixed_width(const uint8_t* bytes, int64_t n_bytes, const int64
                               int32_t width, int32_t mode, uint8_t* out, int64_t* offsets_out,
                               int32_t* status, hipStream_t s);
 
+// data-structure ablation: whole-sub-array OETS, packed keys or text (k_layout.hip)
+hipError_t launch_layout_oets(const uint8_t* bytes, int64_t n_bytes, const int64_t* offsets,
+                              int32_t n_words, int32_t max_len, const int32_t* counts,
+                              const int32_t* starts, const int32_t* order, int32_t* perm,
+                              int32_t layout, int32_t* status, hipStream_t s);
+
 // pre-processing, raw text to words (k_tokenize.hip)
 size_t tok_workspace_bytes(int64_t n_bytes);
 hipError_t launch_tokenize(const uint8_t* text, int64_t n_bytes, uint8_t* out, int64_t* offsets,
