@@ -482,7 +482,8 @@ constexpr int kMaxDevices = 64;
 
 struct FanPool {
     std::mutex mu;
-    bool ready = false;
+    bool ready = false;             // streams and fork/join events
+    bool rb_ready = false;          // phase-count read-back event and pinned word
     hipStream_t aux[kFan - 1] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kFan - 1] = {};
@@ -506,15 +507,22 @@ static int fan_pool_for(int dev, hipStream_t s) {
     return k;
 }
 
+static hipError_t fan_init_readback(FanPool& f) {
+    if (f.rb_ready) return hipSuccess;
+    hipError_t e = hipEventCreateWithFlags(&f.pmax_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&f.host_pmax, sizeof(int32_t), 0);
+    if (e == hipSuccess) f.rb_ready = true;
+    return e;
+}
+
 static hipError_t fan_init(FanPool& f) {
-    if (f.ready) return hipSuccess;
+    if (f.ready) return fan_init_readback(f);
     hipError_t e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming);
     for (int k = 0; k < kFan - 1 && e == hipSuccess; ++k) {
         e = hipStreamCreateWithFlags(&f.aux[k], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.join[k], hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&f.pmax_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&f.host_pmax, sizeof(int32_t), 0);
+    if (e == hipSuccess) e = fan_init_readback(f);
     if (e == hipSuccess) f.ready = true;
     return e;
 }
@@ -583,11 +591,10 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     if ((e = launch_sort_prep(J, b, s)) != hipSuccess) return e;
     if ((e = rec(1, 1, s)) != hipSuccess) return e;
 
-    // BSORT_FLAG_SERIAL_STAGES: every stage on s, no library stream, no
-    // read-back (the merge-split launches its phase bound)
+    // BSORT_FLAG_SERIAL_STAGES: every stage on s and no library stream
     const bool fan = !(b.flags & BSORT_FLAG_SERIAL_STAGES);
     bool readback = false;
-    if (fan && d_pmax && b.phase_bound > 4 && !(b.flags & kFlagTilesOnly)) {
+    if (d_pmax && b.phase_bound > 4 && !(b.flags & kFlagTilesOnly)) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return e;
         readback = cs == hipStreamCaptureStatusNone;
@@ -597,9 +604,9 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     FanPool& f = g_fan[dev][fan ? fan_pool_for(dev, s) : 0];
     std::unique_lock<std::mutex> lock(f.mu, std::defer_lock);
-    if (fan) {
+    if (fan || readback) {
         lock.lock();
-        if ((e = fan_init(f)) != hipSuccess) return e;
+        if ((e = fan ? fan_init(f) : fan_init_readback(f)) != hipSuccess) return e;
     }
     if (readback) {
         if ((e = hipMemcpyAsync(f.host_pmax, d_pmax, sizeof(int32_t), hipMemcpyDeviceToHost,
