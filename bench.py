@@ -729,7 +729,7 @@ def main():
             "unit": "TOP/s", "frac": lds_ce / (lds_span / 1e3) / 1e12 / PEAK_INT32_TOPS}
     elif dom == "merge_split" and merge_bytes:
         achieved = merge_bytes / (stage_ms[dom] / 1e3) / 1e9
-        roof = {"bound": "hbm", "kernel": "k_merge_phase", "achieved": achieved,
+        roof = {"bound": "hbm", "kernel": "k_merge_pairs", "achieved": achieved,
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                 "traffic": None, "bytes_per_step": merge_bytes}
 

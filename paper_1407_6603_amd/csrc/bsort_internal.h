@@ -255,40 +255,6 @@ __device__ __forceinline__ bool chunk_range(const Job* J, int64_t c, int& r, int
     return true;
 }
 
-// Lexicographic a > b over D dwords, a[0] most significant.  Adjacent dwords
-// are compared as one uint64, from the least significant end up.
-template <int D>
-__device__ __forceinline__ bool rec_gt(const uint32_t (&a)[D], const uint32_t (&b)[D]) {
-    bool g;
-    if constexpr (D & 1) {
-        g = a[D - 1] > b[D - 1];
-    } else {
-        uint64_t pa = ((uint64_t)a[D - 2] << 32) | a[D - 1];
-        uint64_t pb = ((uint64_t)b[D - 2] << 32) | b[D - 1];
-        g = pa > pb;
-    }
-    constexpr int qtop = (D & 1) ? D / 2 - 1 : D / 2 - 2;
-#pragma unroll
-    for (int q = qtop; q >= 0; --q) {
-        uint64_t pa = ((uint64_t)a[2 * q] << 32) | a[2 * q + 1];
-        uint64_t pb = ((uint64_t)b[2 * q] << 32) | b[2 * q + 1];
-        g = (pa > pb) | ((pa == pb) & g);
-    }
-    return g;
-}
-
-// compare-exchange: afterwards a <= b
-template <int D>
-__device__ __forceinline__ void cex(uint32_t (&a)[D], uint32_t (&b)[D]) {
-    bool s = rec_gt<D>(a, b);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        uint32_t x = a[d], y = b[d];
-        a[d] = s ? y : x;
-        b[d] = s ? x : y;
-    }
-}
-
 // W = ceil(L/8) big-endian uint64 lanes of the L bytes at p; bytes past L are
 // zero.  Aligned dword loads when the covering dwords lie inside [lo, hi);
 // single bytes otherwise.
