@@ -340,6 +340,38 @@ __device__ __forceinline__ void sort_tile_any(const Src& src, int n, int lane) {
     sort_tile_k<D, 2, KCAP>(src, n, lane, (n + kWave - 1) / kWave);
 }
 
+// Two-dword records compared whole (key dwords of a 5- or 6-byte word, its
+// position in the sub-array in the low 16 bits of the second, which the key
+// leaves zero): the exact fp64 form when the wave's records allow it, else
+// the three-dword integer tile sort, whose key is exactly these two dwords
+// (the third plane is carried along unused).  Padding records (all ones)
+// sort last.
+template <int K, class Src>
+__device__ __forceinline__ void sort_tile_full2(const Src& src, int n, int lane) {
+    uint32_t r[K][2];
+    src.template load<2, K>(r, lane);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (lane * K + k < n && (r[k][0] >= kF64KeyLimit || r[k][1] >= 0x80000000u)) ok = false;
+    if (__all(ok)) {
+        phases_f64<K>(r, n);
+        src.template store<2, K>(r, lane);
+    } else {
+        sort_tile<3, K>(src, n, lane);
+    }
+}
+
+template <int K, int KCAP, class Src>
+__device__ __forceinline__ void sort_tile_full2_k(const Src& src, int n, int lane, int kneed) {
+    if constexpr (K * 2 > KCAP) {
+        sort_tile_full2<K>(src, n, lane);
+    } else {
+        if (kneed <= K) sort_tile_full2<K>(src, n, lane);
+        else sort_tile_full2_k<K * 2, KCAP>(src, n, lane, kneed);
+    }
+}
+
 template <int D>
 __device__ __forceinline__ void run_tile(const Job* J, const TileDesc& t, bool wk, int lane) {
     HbmTile src{gp(J->keys) + t.key_off, gp(J->perm) + t.pos0, t.n_b, t.t0, t.n, wk};
@@ -407,12 +439,31 @@ __device__ __forceinline__ void lds_rec(const uint32_t* lds, int cap, int i, uin
 // slots (independent chains), stages their outputs in registers, and
 // writes them after a barrier.
 
-template <int D>
+// The merges compare records by their key dwords (all but the last, the
+// index).  FULL: by all D dwords, for records whose key and position share
+// the dwords (two-dword records of 5- and 6-byte words, below).
+template <int D, bool FULL = false>
 __device__ __forceinline__ void lds_key(const uint32_t* lds, int cap, int i, uint32_t (&x)[D]) {
     const int a = lsw(i);
 #pragma unroll
-    for (int d = 0; d < D - 1; ++d) x[d] = lds[d * cap + a];
-    x[D - 1] = 0;
+    for (int d = 0; d < (FULL ? D : D - 1); ++d) x[d] = lds[d * cap + a];
+    if (!FULL) x[D - 1] = 0;
+}
+
+template <int D, bool FULL>
+__device__ __forceinline__ bool rec_gt(const uint32_t (&a)[D], const uint32_t (&b)[D]) {
+    if constexpr (!FULL) {
+        return key_gt<D>(a, b);
+    } else {
+        uint32_t x[D + 1], y[D + 1];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            x[d] = a[d];
+            y[d] = b[d];
+        }
+        x[D] = y[D] = 0;
+        return key_gt<D + 1>(x, y);
+    }
 }
 
 // number of the first `diag` outputs of the pair (lower tile at lo, T
@@ -420,7 +471,7 @@ __device__ __forceinline__ void lds_key(const uint32_t* lds, int cap, int i, uin
 // number of lower records i with lower[i] <= upper[diag-1-i] (this predicate
 // holds on a prefix).  Shrinking-length search, a fixed trip count (T <=
 // 2^logT), no branches; while len > 0 both probes lie inside their tiles.
-template <int D>
+template <int D, bool FULL = false>
 __device__ __forceinline__ int lds_merge_path(const uint32_t* lds, int cap, int lo, int T,
                                               int logT, int nb, int diag) {
     int base = diag - nb > 0 ? diag - nb : 0;
@@ -430,9 +481,9 @@ __device__ __forceinline__ int lds_merge_path(const uint32_t* lds, int cap, int 
         const int half = len >> 1;
         const int i = base + half;
         uint32_t x[D], y[D];
-        lds_key<D>(lds, cap, lo + i, x);
-        lds_key<D>(lds, cap, bq - i, y);
-        const bool take = len > 0 && !key_gt<D>(x, y); // lower[i] <= upper[diag-1-i]
+        lds_key<D, FULL>(lds, cap, lo + i, x);
+        lds_key<D, FULL>(lds, cap, bq - i, y);
+        const bool take = len > 0 && !rec_gt<D, FULL>(x, y); // lower[i] <= upper[diag-1-i]
         base = take ? i + 1 : base;
         len = take ? len - half - 1 : half;
     }
@@ -441,11 +492,11 @@ __device__ __forceinline__ int lds_merge_path(const uint32_t* lds, int cap, int 
 
 // E outputs of the pair starting at output `diag`; positions are absolute:
 // lower tile [lo, ea), upper tile [ea, eb), eb <= n
-template <int D, int E>
+template <int D, int E, bool FULL = false>
 __device__ __forceinline__ void lds_merge_slot(const uint32_t* lds, int cap, int n, int lo,
                                                int T, int logT, int nb, int diag,
                                                uint32_t (&out)[E][D]) {
-    const int ia0 = lds_merge_path<D>(lds, cap, lo, T, logT, nb, diag);
+    const int ia0 = lds_merge_path<D, FULL>(lds, cap, lo, T, logT, nb, diag);
     const int ea = lo + T, eb = ea + nb;
     int pa = lo + ia0, pb = ea + (diag - ia0);
     uint32_t ca[D], cb[D];
@@ -454,7 +505,7 @@ __device__ __forceinline__ void lds_merge_slot(const uint32_t* lds, int cap, int
 #pragma unroll
     for (int j = 0; j < E; ++j) {
         // the lower tile's record goes first unless it is exhausted or larger
-        const bool take_a = (pb >= eb) | ((pa < ea) & !key_gt<D>(ca, cb));
+        const bool take_a = (pb >= eb) | ((pa < ea) & !rec_gt<D, FULL>(ca, cb));
         const uint32_t m = take_a ? 0xFFFFFFFFu : 0u;
 #pragma unroll
         for (int d = 0; d < D; ++d) out[j][d] = cb[d] ^ ((ca[d] ^ cb[d]) & m);
@@ -484,14 +535,14 @@ __host__ __device__ constexpr int merge_slot_outputs(int cap, int nt) {
 // range still open and a ballot's popcount says how many whole cells lie
 // inside the prefix; the next round searches the first cell that does not.
 // T is a power of two >= m; rounds: ceil(log64 T), at least one.
-template <int D>
+template <int D, bool FULL = false>
 __device__ __forceinline__ int wave_count_before(const uint32_t* lds, int cap, int at, int m,
                                                  int T, const uint32_t (&x)[D], bool le,
                                                  int lane) {
     auto pred = [&](int i) -> bool {
         uint32_t y[D];
-        lds_key<D>(lds, cap, at + (i < m ? i : m - 1), y);
-        const bool before = le ? !key_gt<D>(y, x) : key_gt<D>(x, y);
+        lds_key<D, FULL>(lds, cap, at + (i < m ? i : m - 1), y);
+        const bool before = le ? !rec_gt<D, FULL>(y, x) : rec_gt<D, FULL>(x, y);
         return i < m && before;
     };
     int base = 0;
@@ -509,7 +560,7 @@ constexpr int kMergeWinWords = 4 * kMaxPairs + 1;
 
 // WIN: trim each pair to its changing window first (two ballot searches and
 // two barriers per phase; pays off where pairs are many and long)
-template <int D, int NT, int CAP, bool WIN>
+template <int D, int NT, int CAP, bool WIN, bool FULL = false>
 __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, int s, int tid,
                                 int* win) {
     constexpr int E = merge_slot_outputs(CAP, NT);        // outputs per slot
@@ -534,12 +585,12 @@ __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, in
             const int lo = (off + 2 * k) << logT;
             const int nb = n - lo - T < T ? n - lo - T : T;
             uint32_t b0[D], alast[D];
-            lds_key<D>(lds, CAP, lo + T, b0);
-            lds_key<D>(lds, CAP, lo + T - 1, alast);
-            const int j0 = wave_count_before<D>(lds, CAP, lo, T, T, b0, true, lane);
-            const int j1 = wave_count_before<D>(lds, CAP, lo + T, nb, T, alast, false, lane);
+            lds_key<D, FULL>(lds, CAP, lo + T, b0);
+            lds_key<D, FULL>(lds, CAP, lo + T - 1, alast);
+            const int j0 = wave_count_before<D, FULL>(lds, CAP, lo, T, T, b0, true, lane);
+            const int j1 = wave_count_before<D, FULL>(lds, CAP, lo + T, nb, T, alast, false, lane);
             if (lane == 0) {
-                const bool moves = key_gt<D>(alast, b0);
+                const bool moves = rec_gt<D, FULL>(alast, b0);
                 wlo[k] = lo + j0;
                 wna[k] = moves ? T - j0 : 0;
                 wnb[k] = moves ? j1 : 0;
@@ -574,7 +625,7 @@ __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, in
                 const int diag = (q - slot0[k]) * E;
                 pos[r] = wlo[k] + diag;
                 cnt[r] = na + nbw - diag < E ? na + nbw - diag : E;
-                lds_merge_slot<D, E>(lds, CAP, n, wlo[k], na, logT, nbw, diag, out[r]);
+                lds_merge_slot<D, E, FULL>(lds, CAP, n, wlo[k], na, logT, nbw, diag, out[r]);
             }
         }
     } else {
@@ -590,7 +641,7 @@ __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, in
                 const int a = off + (((pos[r] - U0) >> (logT + 1)) << 1);   // pair's lower tile
                 const int lo = a << logT;
                 const int nb = n - lo - T < T ? n - lo - T : T;
-                lds_merge_slot<D, E>(lds, CAP, n, lo, T, logT, nb, pos[r] - lo, out[r]);
+                lds_merge_slot<D, E, FULL>(lds, CAP, n, lo, T, logT, nb, pos[r] - lo, out[r]);
             }
         }
     }
@@ -640,6 +691,11 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         const int64_t ks = bk.stride;                  // key lane stride
         const gptr<uint64_t> keys = gp(J->keys) + bk.key_off;
         const gptr<int32_t> perm = gp(J->perm) + bk.pos0;
+        // 5- and 6-byte words whose keys are not written back: a record is
+        // the two key dwords with the word's position (n <= CAP < 2^16) in
+        // the zero low half of the second, compared whole; the index comes
+        // from the position at the end
+        const bool full2 = D == 3 && bk.L <= 6 && !bk.wk;    // uniform
 #pragma unroll 4
         for (int i = tid; i < n; i += NT) {
             const int a = lsw(i);
@@ -647,9 +703,9 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
             for (int w = 0; w < W; ++w) {
                 const uint64_t v = keys[w * ks + i];
                 lds[(2 * w) * CAP + a] = (uint32_t)(v >> 32);
-                if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + a] = (uint32_t)v;
+                if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + a] = (uint32_t)v | (full2 ? i : 0);
             }
-            lds[Dk * CAP + a] = (uint32_t)perm[i];
+            if (!full2) lds[Dk * CAP + a] = (uint32_t)perm[i];
         }
         __syncthreads();
         const int p = (n + T - 1) / T;
@@ -657,9 +713,33 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
             const int t0 = t * T;
             const int tn = n - t0 < T ? n - t0 : T;
             LdsTile src{lds, CAP, t0, tn};
+            if constexpr (D == 3) {
+                if (full2) {
+                    sort_tile_full2_k<2, KCAP>(src, tn, lane, (tn + kWave - 1) / kWave);
+                    continue;
+                }
+            }
             sort_tile_any<D, KCAP>(src, tn, lane);
         }
         __syncthreads();
+        if constexpr (D == 3) {
+            if (full2) {
+                if (!tiles_only)
+                    for (int s = 0; s < p; ++s)
+                        lds_merge_phase<2, NT, CAP, (CAP >= 8192), true>(lds, n, T, logT, p, s,
+                                                                         tid, mwin);
+                // each output's index from its position, gathered into the
+                // free third plane before any is written over
+                for (int i = tid; i < n; i += NT) {
+                    const int a = lsw(i);
+                    lds[2 * CAP + a] = (uint32_t)perm[(int)(lds[CAP + a] & 0xFFFFu)];
+                }
+                __syncthreads();
+                for (int i = tid; i < n; i += NT) perm[i] = (int32_t)lds[2 * CAP + lsw(i)];
+                __syncthreads();                       // LDS reused by the next sub-array
+                continue;
+            }
+        }
         if (!tiles_only)
             for (int s = 0; s < p; ++s)
                 lds_merge_phase<D, NT, CAP, (CAP >= 8192)>(lds, n, T, logT, p, s, tid, mwin);
