@@ -288,6 +288,32 @@ def test_zero_one_lds_classes(bs, ws, L):
     assert np.array_equal(got, zero_one_expect(seqs))
 
 
+@pytest.mark.parametrize("alphabet", [b"eatonsEAT", None, b"ab\x7f\x80\xff"])
+def test_five_six_byte_words_in_every_class(bs, ws, alphabet):
+    """5- and 6-byte words, whose in-LDS records carry the word's position in
+    the key's spare low bits: letters (exact fp64 tiles), all byte values and
+    bytes at and above 0x7F (the integer fallback for some or all tiles),
+    heavy duplicates, sizes at every three-dword size class and past the
+    largest (merged through HBM, without the spare-bit form)."""
+    rng = np.random.default_rng(56)
+    lists = []
+    for cap in lds_caps(3) + [12288 + 129]:
+        for L in (5, 6):
+            for n in (cap - 1, cap // 2 + 3):
+                if alphabet is None:
+                    w = wordgen.random_words(rng, n, L, L)
+                else:
+                    # a few distinct words, so ties are everywhere
+                    pool = wordgen.random_words(rng, 40, L, L, alphabet=alphabet).as_list()
+                    w = wordgen.Words.from_list([pool[i] for i in rng.integers(0, 40, n)])
+                lists.append(w)
+    batch = wordgen.Batch.concat(lists)
+    expect = oracle.definition_sort_batch(batch.bytes, batch.offsets, batch.req_start, 16)
+    for T in (128, 512):
+        got = gpu_batch(bs, ws, batch, 6, tune=bs.tuning(T, 0))
+        assert np.array_equal(got, expect), T
+
+
 def test_large_serve_request_merged_through_hbm(bs, ws):
     """A 1,000,000-word request of the serving workload (lengths to 32, one
     200,000-word vocabulary): its large sub-arrays are cut into chunks sorted
