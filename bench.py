@@ -40,16 +40,16 @@ PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 128 B/clk/CU LDS bandwidth: 78.6
 SORT_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TOK_SOURCES = ("paper_1407_6603_amd/csrc/k_tokenize.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TRAFFIC = {
-    "k_bucket_lds<2, 1024, 16384>": {"read": 66615591, "write": 22064384,
-                                     "files": SORT_SOURCES, "sources": "a2ddf5039f339c12"},
-    "k_bucket_lds<3, 1024, 8192>": {"read": 38453402, "write": 12693760,
-                                    "files": SORT_SOURCES, "sources": "a2ddf5039f339c12"},
-    "k_tok_count": {"read": 189689291, "write": 749648,
-                    "files": TOK_SOURCES, "sources": "365517177ff34074"},
+    "k_bucket_lds<2, 1024, 16384>": {"read": 66613697, "write": 22064224,
+                                     "files": SORT_SOURCES, "sources": "092f8726b0c782ac"},
+    "k_bucket_lds<3, 1024, 8192>": {"read": 38670586, "write": 12693760,
+                                    "files": SORT_SOURCES, "sources": "092f8726b0c782ac"},
+    "k_tok_count": {"read": 189705992, "write": 746752,
+                    "files": TOK_SOURCES, "sources": "07a07d14a136403b"},
     "k_tok_scan": {"read": 110202, "write": 183712,
-                   "files": TOK_SOURCES, "sources": "365517177ff34074"},
-    "k_tok_write": {"read": 191124352, "write": 403948624,
-                    "files": TOK_SOURCES, "sources": "365517177ff34074"},
+                   "files": TOK_SOURCES, "sources": "07a07d14a136403b"},
+    "k_tok_write": {"read": 191124287, "write": 403955360,
+                    "files": TOK_SOURCES, "sources": "07a07d14a136403b"},
 }
 
 
