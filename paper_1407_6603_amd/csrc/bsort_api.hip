@@ -75,7 +75,7 @@ bool make_layout(int64_t total, int32_t R, int32_t max_len, Layout& L) {
     L.tile_count = take(sizeof(int32_t) * kNumD);
     L.lb_cap = 4 * (int64_t)R + 1;                    // a width class covers 4 lengths per list
     L.lbuckets = take(sizeof(LBucket) * (size_t)L.lb_cap * (kLdsMaxD + 1) * kLdsClasses);
-    L.lb_count = take(sizeof(int32_t) * kNumD * kLdsClasses);
+    L.lb_count = take(sizeof(int32_t) * 3 * kNumD * kLdsClasses);   // count, back, take
     for (int D = 2; D <= L.dmax && D <= kLdsMaxD; ++D)
         L.hchunks[D] = take(sizeof(LBucket) * (size_t)L.tile_cap);
     L.hc_count = take(sizeof(int32_t) * (kLdsMaxD + 1));
@@ -191,6 +191,8 @@ Job base_job(const Layout& L, char* ws, const Bounds& b) {
     j.pmax = (int32_t*)(ws + L.pmax);
     j.lbuckets = (LBucket*)(ws + L.lbuckets);
     j.lb_count = (int32_t*)(ws + L.lb_count);
+    j.lb_back = j.lb_count + kNumD * kLdsClasses;
+    j.lb_take = j.lb_back + kNumD * kLdsClasses;
     j.lb_cap = L.lb_cap;
     j.tile_count = (int32_t*)(ws + L.tile_count);
     j.mlist[0] = (MergeItem*)(ws + L.mlist[0]);

@@ -73,6 +73,17 @@ __host__ __device__ constexpr int lds_cap(int c, int D) {
 __host__ __device__ constexpr bool lds_fits(int D, int c) {
     return D >= 2 && D <= kLdsMaxD && D * 4 * lds_cap(c, D) <= kLdsBytes;
 }
+// Sub-arrays of class c hold more than this many words: the next smaller
+// class's capacity, else the single-tile size.  A class's list holds its
+// larger sub-arrays (above a quarter of the way from this floor to the
+// capacity) first, so that workgroups taking entries in list order start
+// the longest sorts early and end together.
+__host__ __device__ constexpr int lds_class_floor(int c, int D, int tile) {
+    return c > 0 && lds_cap(c - 1, D) > tile ? lds_cap(c - 1, D) : tile;
+}
+__host__ __device__ constexpr bool lds_class_large(int n, int c, int D, int tile) {
+    return n > lds_class_floor(c, D, tile) + (lds_cap(c, D) - lds_class_floor(c, D, tile)) / 4;
+}
 // threads per workgroup: 1024 only where the staged merge outputs still fit
 // the 128 VGPRs a 1024-thread workgroup leaves each lane (D <= 3) and LDS
 // holds one workgroup per CU anyway; 512 for two-dword records up to 8192
@@ -180,8 +191,13 @@ struct Job {
     int32_t tile_keys[kNumD];    // tile size per D: single tiles and in-LDS sub-arrays
     int32_t hbm_tile_keys[kNumD];  // tile size of sub-arrays merged through HBM
     int32_t* tile_count;         // [kNumD]
+    // per class list: the larger sub-arrays from the front (lb_count of
+    // them), the smaller from the back (lb_back, in reverse); the class
+    // kernel's workgroups take list entries in that order through lb_take
     LBucket* lbuckets;           // [kNumD * kLdsClasses][lb_cap]
     int32_t* lb_count;           // [kNumD * kLdsClasses]
+    int32_t* lb_back;            // [kNumD * kLdsClasses]
+    int32_t* lb_take;            // [kNumD * kLdsClasses]
     int64_t lb_cap;
     // chunks of sub-arrays merged through HBM, sorted in LDS first (D <= kLdsMaxD)
     LBucket* hchunks[kLdsMaxD + 1];   // [tile_cap[D]] each

@@ -672,21 +672,44 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // list < kLdsClasses: the sub-arrays of that size class; list ==
     // kLdsClasses: chunks of sub-arrays that are merged through HBM next
-    int64_t cnt;
+    // a size class's list: entries [0, front) from the front, the rest from
+    // the back in reverse, taken one at a time through a counter (larger
+    // sub-arrays first, each workgroup taking the next when it is free);
+    // chunks merged through HBM next: strided over the grid
+    int64_t cnt, front;
     const LBucket* lst;
+    int32_t* take = nullptr;
     if (list < kLdsClasses) {
         const int slot = D * kLdsClasses + list;
-        cnt = J->lb_count[slot] < J->lb_cap ? J->lb_count[slot] : J->lb_cap;
+        const int64_t nf = J->lb_count[slot], nk = J->lb_back[slot];
+        front = nf < J->lb_cap ? nf : J->lb_cap;
+        cnt = nf + nk < J->lb_cap ? nf + nk : J->lb_cap;
         lst = J->lbuckets + slot * J->lb_cap;
+        take = J->lb_take + slot;
     } else {
         cnt = J->hc_count[D] < J->tile_cap[D] ? J->hc_count[D] : J->tile_cap[D];
+        front = cnt;
         lst = J->hchunks[D];
     }
+    __shared__ int next_entry;
     const bool tiles_only = (J->flags & kFlagTilesOnly) != 0;
     const int T = tiles_only ? J->tile_keys[D] : lds_tile(J->tile_keys[D], CAP, D);
     const int logT = 31 - __builtin_clz(T);               // tile sizes are powers of two
-    for (int64_t bi = blockIdx.x; bi < cnt; bi += gridDim.x) {
-        const LBucket bk = lst[bi];
+    for (int64_t it = 0;; ++it) {
+        int64_t bi;
+        if (take) {                                       // uniform
+            // every pass ends with a barrier, so all threads have read the
+            // previous entry before thread 0 writes the next
+            if (tid == 0)
+                next_entry = __hip_atomic_fetch_add(gp(take), 1, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            bi = next_entry;
+        } else {
+            bi = blockIdx.x + it * gridDim.x;
+        }
+        if (bi >= cnt) break;
+        const LBucket bk = lst[bi < front ? bi : J->lb_cap - 1 - (bi - front)];
         const int n = bk.n_b;                          // n <= CAP (checked when listed)
         const int64_t ks = bk.stride;                  // key lane stride
         const gptr<uint64_t> keys = gp(J->keys) + bk.key_off;

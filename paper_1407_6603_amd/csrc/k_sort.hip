@@ -22,7 +22,11 @@ __global__ __launch_bounds__(256) void k_sort_init(const Job* __restrict__ J) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     if (i0 < kNumD) J->tile_count[i0] = 0;
-    if (i0 < kNumD * kLdsClasses) J->lb_count[i0] = 0;
+    if (i0 < kNumD * kLdsClasses) {
+        J->lb_count[i0] = 0;
+        J->lb_back[i0] = 0;
+        J->lb_take[i0] = 0;
+    }
     if (i0 <= kLdsMaxD) J->hc_count[i0] = 0;
     if (i0 == 0) J->pmax[0] = 0;
     // phase counters in use: every sub-array needs fewer than phase_bound phases
@@ -38,13 +42,14 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     __shared__ int64_t blk_tile_base[kNumD];
     __shared__ int blk_items;
     __shared__ int64_t blk_item_base;
-    __shared__ int blk_lb[kNumD * kLdsClasses];
-    __shared__ int64_t blk_lb_base[kNumD * kLdsClasses];
+    constexpr int kLb = kNumD * kLdsClasses;          // front counts, then back counts
+    __shared__ int blk_lb[2 * kLb];
+    __shared__ int64_t blk_lb_base[2 * kLb];
     __shared__ int blk_hc[kLdsMaxD + 1];
     __shared__ int64_t blk_hc_base[kLdsMaxD + 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid < kNumD) blk_tiles[tid] = 0;
-    if (tid < kNumD * kLdsClasses) blk_lb[tid] = 0;
+    if (tid < 2 * kLb) blk_lb[tid] = 0;
     if (tid <= kLdsMaxD) blk_hc[tid] = 0;
     if (tid == 0) blk_items = 0;
     __syncthreads();
@@ -95,7 +100,8 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
             } else if (c >= 0) {
                 route[k] = 2;
                 lcls[k] = c;
-                tslot[k] = atomicAdd(&blk_lb[D * kLdsClasses + c], 1);
+                const bool front = lds_class_large(nb, c, D, J->tile_keys[D]);
+                tslot[k] = atomicAdd(&blk_lb[(front ? 0 : kLb) + D * kLdsClasses + c], 1);
             } else {
                 // merged through HBM: chunks sorted in LDS (D <= kLdsMaxD) or
                 // register tiles, then nt merge-split phases
@@ -115,8 +121,9 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     if (tid < kNumD && blk_tiles[tid] > 0)
         blk_tile_base[tid] = atomicAdd(&J->tile_count[tid], blk_tiles[tid]);
     if (tid == kNumD && blk_items > 0) blk_item_base = atomicAdd(&J->mcount[0], blk_items);
-    if (tid < kNumD * kLdsClasses && blk_lb[tid] > 0)
-        blk_lb_base[tid] = atomicAdd(&J->lb_count[tid], blk_lb[tid]);
+    if (tid < 2 * kLb && blk_lb[tid] > 0)
+        blk_lb_base[tid] = atomicAdd(tid < kLb ? &J->lb_count[tid] : &J->lb_back[tid - kLb],
+                                     blk_lb[tid]);
     if (tid <= kLdsMaxD && blk_hc[tid] > 0)
         blk_hc_base[tid] = atomicAdd(&J->hc_count[tid], blk_hc[tid]);
     __syncthreads();
@@ -131,8 +138,11 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
         const int64_t ko = kos[wv][L];
         if (route[k] == 2) {
             const int sl = D * kLdsClasses + lcls[k];
-            const int64_t at = blk_lb_base[sl] + tslot[k];
-            if (at >= J->lb_cap) {
+            const bool front = lds_class_large(nb, lcls[k], D, J->tile_keys[D]);
+            const int64_t at0 = blk_lb_base[(front ? 0 : kLb) + sl] + tslot[k];
+            const int64_t at = front ? at0 : J->lb_cap - 1 - at0;
+            // front and back together hold at most 4 per list, fewer than lb_cap
+            if (at0 >= J->lb_cap) {
                 set_status(J, ST_OVERFLOW);
                 continue;
             }
