@@ -492,10 +492,11 @@ __device__ __forceinline__ int lds_merge_path(const uint32_t* lds, int cap, int 
 
 // E outputs of the pair starting at output `diag`; positions are absolute:
 // lower tile [lo, ea), upper tile [ea, eb), eb <= n
+// (at most e <= E of them: e is uniform over the wave)
 template <int D, int E, bool FULL = false>
 __device__ __forceinline__ void lds_merge_slot(const uint32_t* lds, int cap, int n, int lo,
                                                int T, int logT, int nb, int diag,
-                                               uint32_t (&out)[E][D]) {
+                                               uint32_t (&out)[E][D], int e = E) {
     const int ia0 = lds_merge_path<D, FULL>(lds, cap, lo, T, logT, nb, diag);
     const int ea = lo + T, eb = ea + nb;
     int pa = lo + ia0, pb = ea + (diag - ia0);
@@ -504,21 +505,23 @@ __device__ __forceinline__ void lds_merge_slot(const uint32_t* lds, int cap, int
     lds_rec<D>(lds, cap, pb < n ? pb : n - 1, cb);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-        // the lower tile's record goes first unless it is exhausted or larger
-        const bool take_a = (pb >= eb) | ((pa < ea) & !rec_gt<D, FULL>(ca, cb));
-        const uint32_t m = take_a ? 0xFFFFFFFFu : 0u;
+        if (j < e) {
+            // the lower tile's record goes first unless it is exhausted or larger
+            const bool take_a = (pb >= eb) | ((pa < ea) & !rec_gt<D, FULL>(ca, cb));
+            const uint32_t m = take_a ? 0xFFFFFFFFu : 0u;
 #pragma unroll
-        for (int d = 0; d < D; ++d) out[j][d] = cb[d] ^ ((ca[d] ^ cb[d]) & m);
-        pa += take_a ? 1 : 0;
-        pb += take_a ? 0 : 1;
-        int nx = take_a ? pa : pb;
-        nx = nx < n ? nx : n - 1;            // past the end: any record, never taken
-        uint32_t x[D];
-        lds_rec<D>(lds, cap, nx, x);
+            for (int d = 0; d < D; ++d) out[j][d] = cb[d] ^ ((ca[d] ^ cb[d]) & m);
+            pa += take_a ? 1 : 0;
+            pb += take_a ? 0 : 1;
+            int nx = take_a ? pa : pb;
+            nx = nx < n ? nx : n - 1;        // past the end: any record, never taken
+            uint32_t x[D];
+            lds_rec<D>(lds, cap, nx, x);
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            ca[d] = ca[d] ^ ((x[d] ^ ca[d]) & m);
-            cb[d] = x[d] ^ ((cb[d] ^ x[d]) & m);
+            for (int d = 0; d < D; ++d) {
+                ca[d] = ca[d] ^ ((x[d] ^ ca[d]) & m);
+                cb[d] = x[d] ^ ((cb[d] ^ x[d]) & m);
+            }
         }
     }
 }
@@ -660,10 +663,68 @@ __device__ void lds_merge_phase(uint32_t* lds, int n, int T, int logT, int p, in
     __syncthreads();
 }
 
+// One merge-split phase with each pair owned by one wave (tiles of at most
+// kLdsMaxTile records, so a pair's window gives each lane at most
+// kWaveRunMax outputs).  The wave finds the pair's window (as above), gives
+// each lane an equal run of its outputs, and writes them back once all its
+// lanes have read: a wave's LDS operations complete in order and pairs are
+// disjoint, so one barrier ends the phase.
+constexpr int kWaveRunMax = 2 * kLdsMaxTile / kWave;
+
+template <int D, int NT, int CAP, bool FULL = false>
+__device__ void lds_merge_phase_waves(uint32_t* lds, int n, int T, int logT, int p, int s,
+                                      int tid) {
+    constexpr int NW = NT / kWave;
+    const int off = s & 1;
+    if (p - 2 < off) return;                              // no pair in this phase (uniform)
+    const int np = (p - 2 - off) / 2 + 1;                 // pairs a = off, off+2, ...
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int k = wv; k < np; k += NW) {                   // uniform over the wave
+        const int lo = (off + 2 * k) << logT;
+        const int nb = n - lo - T < T ? n - lo - T : T;
+        uint32_t b0[D], alast[D];
+        lds_key<D, FULL>(lds, CAP, lo + T, b0);
+        lds_key<D, FULL>(lds, CAP, lo + T - 1, alast);
+        if (!rec_gt<D, FULL>(alast, b0)) continue;       // already in order across the seam
+        const int j0 = wave_count_before<D, FULL>(lds, CAP, lo, T, T, b0, true, lane);
+        const int j1 = wave_count_before<D, FULL>(lds, CAP, lo + T, nb, T, alast, false, lane);
+        const int wlo = lo + j0, na = T - j0;
+        const int m = na + j1;                            // window outputs, <= 2T
+        const int e = (m + kWave - 1) / kWave;            // per lane, <= kWaveRunMax
+        const int diag = lane * e;
+        const int cnt = m - diag < e ? (m - diag > 0 ? m - diag : 0) : e;
+        uint32_t out[kWaveRunMax][D];
+        if (cnt > 0) lds_merge_slot<D, kWaveRunMax, FULL>(lds, CAP, n, wlo, na, logT, j1, diag,
+                                                           out, e);
+#pragma unroll
+        for (int j = 0; j < kWaveRunMax; ++j) {
+            if (j < cnt) {
+                const int a = lsw(wlo + diag + j);
+#pragma unroll
+                for (int d = 0; d < D; ++d) lds[d * CAP + a] = out[j][d];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// all p phases of a sub-array in LDS: pairs owned by waves in the classes
+// of 8,192 words and more, slots spread over the workgroup below that
+template <int D, int NT, int CAP, bool FULL = false>
+__device__ __forceinline__ void lds_merge_all(uint32_t* lds, int n, int T, int logT, int p,
+                                              int tid, int* win) {
+    for (int s = 0; s < p; ++s) {
+        if constexpr (CAP >= 8192)
+            lds_merge_phase_waves<D, NT, CAP, FULL>(lds, n, T, logT, p, s, tid);
+        else
+            lds_merge_phase<D, NT, CAP, false, FULL>(lds, n, T, logT, p, s, tid, win);
+    }
+}
+
 template <int D, int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, int list) {
     __shared__ uint32_t lds[D * CAP];
-    __shared__ int mwin[CAP >= 8192 ? kMergeWinWords : 1];
+    __shared__ int mwin[1];                            // (window tables: pair merges only)
     constexpr int NW = NT / kWave;
     constexpr int Dk = D - 1, W = (Dk + 1) / 2;
     constexpr int KCAP = kmax_for(D) < kLdsMaxTile / kWave ? kmax_for(D) : kLdsMaxTile / kWave;
@@ -747,10 +808,7 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         __syncthreads();
         if constexpr (D == 3) {
             if (full2) {
-                if (!tiles_only)
-                    for (int s = 0; s < p; ++s)
-                        lds_merge_phase<2, NT, CAP, (CAP >= 8192), true>(lds, n, T, logT, p, s,
-                                                                         tid, mwin);
+                if (!tiles_only) lds_merge_all<2, NT, CAP, true>(lds, n, T, logT, p, tid, mwin);
                 // each output's index from its position, gathered into the
                 // free third plane before any is written over
                 for (int i = tid; i < n; i += NT) {
@@ -763,9 +821,7 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
                 continue;
             }
         }
-        if (!tiles_only)
-            for (int s = 0; s < p; ++s)
-                lds_merge_phase<D, NT, CAP, (CAP >= 8192)>(lds, n, T, logT, p, s, tid, mwin);
+        if (!tiles_only) lds_merge_all<D, NT, CAP>(lds, n, T, logT, p, tid, mwin);
         for (int i = tid; i < n; i += NT) {
             const int a = lsw(i);
             perm[i] = (int32_t)lds[Dk * CAP + a];
