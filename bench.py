@@ -449,47 +449,24 @@ def main():
     tune = bs.tuning(tile, 0, 0, hbm_tile)
     stream = torch.cuda.current_stream()
     ws = bs.Workspace(bs.workspace_bytes(total, max_len, batch.R), dev)
-    # one set of stage events per timed step, created (and first recorded) now
-    timers = [bs.StageTimer(max_len, stream) for _ in range(max(args.steps, 1))]
+    struct, merge_bytes, phases_max = workload_structure(
+        batch.offsets, batch.req_start, max_len, tile or 256, 2048)
 
     def step(timer):
         bs.sort_batch_staged(b_t, o_t, rs_t, batch.req_start, max_len, timer, tune, ws, out=perm)
 
+    untimed = bs.StageTimer(max_len, stream, only=())
     for _ in range(args.warmup):
-        step(timers[0])
+        step(untimed)
     torch.cuda.synchronize()
     bs.check_device_status(ws)
-
-    # ---- timed region: K steps back to back on one stream; HIP events
-    # between the stages of every step, read after the region
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for k in range(args.steps):
-        step(timers[k])
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    stage_sum = {}
-    lds_span = 0.0
-    for k in range(args.steps):
-        for name, v in timers[k].ms().items():
-            stage_sum[name] = stage_sum.get(name, 0.0) + v
-        lds_span += timers[k].span_ms(lambda n: n.startswith("lds_"))
-    stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
-    lds_span /= args.steps
-    value = total / (ms_per_step / 1e3)
-    bs.check_device_status(ws)
-    got = perm.cpu().numpy()
-    if cu_scaling is not None and "rows" in cu_scaling:
-        import hashlib
-        sha = hashlib.sha256(got.tobytes()).hexdigest()[:16]
-        cu_scaling["identical"] = all(r["perm_sha"] == sha for r in cu_scaling["rows"])
 
     # ---- per-stage times with each stage alone on the GPU (every stage in
-    # order on one stream); the timed region above runs them side by side
+    # order on one stream); the timed region below runs them side by side
     serial = None
+    sperm = None
     if not args.no_serial:
         stune = bs.tuning(tile, 0, bs.FLAG_SERIAL_STAGES, hbm_tile)
         sperm = torch.empty(total, dtype=torch.int32, device=dev)
@@ -510,9 +487,59 @@ def main():
             for name, v in t.ms().items():
                 ssum[name] = ssum.get(name, 0.0) + v
         serial = {"ms_per_step": ev0.elapsed_time(ev1) / reps, "steps": reps,
-                  "stage_ms": {k: v / reps for k, v in ssum.items()},
-                  "identical": bool(np.array_equal(sperm.cpu().numpy(), got))}
-        del sperm
+                  "stage_ms": {k: v / reps for k, v in ssum.items()}}
+
+    # ---- per-stage times side by side: every stage's events recorded (each
+    # event is a marker in its stream, so these steps run a little slower
+    # than the timed region's)
+    timers = [bs.StageTimer(max_len, stream) for _ in range(max(args.steps, 1))]
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for k in range(args.steps):
+        step(timers[k])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    all_events_ms = ev0.elapsed_time(ev1) / args.steps
+    stage_sum = {}
+    lds_span = 0.0
+    for k in range(args.steps):
+        for name, v in timers[k].ms().items():
+            stage_sum[name] = stage_sum.get(name, 0.0) + v
+        lds_span += timers[k].span_ms(lambda n: n.startswith("lds_"))
+    stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
+    lds_span /= args.steps
+    bs.check_device_status(ws)
+
+    # the dominant kernel is the one with the most work: the longest launch
+    # with the GPU to itself (the serial leg), among stages that have work on
+    # this input.  Side by side a launch's duration includes waiting for CUs
+    # that other stages hold (the short tile sorts queue behind the in-LDS
+    # classes), so that time alone would pick the wrong kernel.
+    worked = [k for k in stage_ms if k in struct or (k == "merge_split" and merge_bytes)]
+    alone = serial["stage_ms"] if serial else stage_ms
+    dom = max(worked, key=lambda k: alone.get(k, 0.0))
+
+    # ---- timed region: K steps back to back on one stream, HIP events
+    # around the dominant stage's launch only (read after the region)
+    dtimers = [bs.StageTimer(max_len, stream, only={dom}) for _ in range(max(args.steps, 1))]
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for k in range(args.steps):
+        step(dtimers[k])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    dom_ms = sum(t.ms()[dom] for t in dtimers[:args.steps]) / args.steps
+    value = total / (ms_per_step / 1e3)
+    bs.check_device_status(ws)
+    got = perm.cpu().numpy()
+    if serial is not None:
+        serial["identical"] = bool(np.array_equal(sperm.cpu().numpy(), got))
+    del sperm
+    if cu_scaling is not None and "rows" in cu_scaling:
+        import hashlib
+        sha = hashlib.sha256(got.tobytes()).hexdigest()[:16]
+        cu_scaling["identical"] = all(r["perm_sha"] == sha for r in cu_scaling["rows"])
 
     # ---- the same batch through a captured graph plan (one graph launch per step)
     graph = None
@@ -681,25 +708,13 @@ def main():
                         "others against a stable library sort on 16 sampled lists"}
         del uws
 
-    # ---- roofline of the dominant kernel (the stage with the largest time;
-    # every tile and in-LDS stage is exactly one kernel launch)
-    struct, merge_bytes, phases_max = workload_structure(
-        batch.offsets, batch.req_start, max_len, tile or 256, 2048)
-    # stages run side by side after the pack, so a launch's duration in the
-    # timed region includes waiting for CUs that other stages hold (the short
-    # tile sorts queue behind the in-LDS classes).  The dominant kernel is the
-    # one with the most work: the longest launch with the GPU to itself (the
-    # serial leg), among stages that have work on this input; its rate below
-    # uses its launch duration in the timed region.
-    worked = {k: v for k, v in stage_ms.items()
-              if k in struct or (k == "merge_split" and merge_bytes)}
-    alone = serial["stage_ms"] if serial else stage_ms
-    dom = max(worked, key=lambda k: alone.get(k, 0.0))
+    # ---- roofline of the dominant kernel (chosen above; every tile and in-LDS
+    # stage is exactly one kernel launch), at its launch time in the timed region
     roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": None, "traffic": None}
     if dom in struct:
         w = struct[dom]
-        D, ce, sec = w["D"], w["ce"], stage_ms[dom] / 1e3
+        D, ce, sec = w["D"], w["ce"], dom_ms / 1e3
         ops = 3 * D * ce                       # D dword compares + 2D dword selects per CE
         achieved = ops / sec / 1e12
         roof = {"bound": "alu", "kernel": kernel_name(dom), "achieved": achieved,
@@ -707,7 +722,7 @@ def main():
                 "traffic": measured_traffic(kernel_name(dom)),
                 # key lanes (8 B each) read, perm read and written (4 + 4 B) per word
                 "hbm_bytes_algorithmic": (8 * (D // 2) + 8) * w["words"],
-                "launch_ms": stage_ms[dom], "launch_ms_alone": alone.get(dom),
+                "launch_ms": dom_ms, "launch_ms_alone": alone.get(dom),
                 "ce_per_launch": ce,
                 "ce_per_s": ce / sec, "ops_per_ce": 3 * D, "words_per_launch": w["words"]}
         # the compare-exchange roofline as an LDS stream: each CE reads and
@@ -728,7 +743,7 @@ def main():
             "achieved": lds_ce / (lds_span / 1e3) / 1e12, "peak": PEAK_INT32_TOPS,
             "unit": "TOP/s", "frac": lds_ce / (lds_span / 1e3) / 1e12 / PEAK_INT32_TOPS}
     elif dom == "merge_split" and merge_bytes:
-        achieved = merge_bytes / (stage_ms[dom] / 1e3) / 1e9
+        achieved = merge_bytes / (dom_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": "k_merge_pairs", "achieved": achieved,
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                 "traffic": None, "bytes_per_step": merge_bytes}
@@ -771,6 +786,7 @@ def main():
         "per_bucket_launch": plain,
         "batched_over_per_bucket": (value / plain["value"]) if plain else None,
         "stage_ms": stage_ms,
+        "all_stage_events_ms_per_step": all_events_ms,
         "serial_stages": serial,
         "tokenize": tok,
         "unbucketed": unb,

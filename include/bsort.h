@@ -182,7 +182,9 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
  * events[2i+1] just after it, on the stream that runs stage i, so
  * hipEventElapsedTime(events[2i], events[2i+1]) is stage i's device time
  * (with other stages running beside it).  n_events must be
- * 2 * bsort_stage_count(b->max_len).  The per-bucket form cannot be staged.
+ * 2 * bsort_stage_count(b->max_len); a NULL entry is not recorded (so a
+ * caller can time only the stages it needs: each recorded event is a marker
+ * in the stream).  The per-bucket form cannot be staged.
  */
 int bsort_stage_count(int32_t max_len);
 const char *bsort_stage_name(int32_t max_len, int i);

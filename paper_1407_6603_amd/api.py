@@ -268,33 +268,42 @@ def stage_names(max_len: int):
 
 class StageTimer:
     """HIP events for bsort_sort_batch_staged: a begin and an end event per
-    stage, recorded on the stream that runs the stage."""
+    stage, recorded on the stream that runs the stage.  ``only``: the names of
+    the stages to time (default all); the others record nothing."""
 
-    def __init__(self, max_len: int, stream=None):
+    def __init__(self, max_len: int, stream=None, only=None):
         self.names = stage_names(max_len)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(self.names))]
-        for e in self.events:              # torch creates the HIP event on first record
-            e.record(self.stream)
-        self.handles = (ctypes.c_void_p * len(self.events))(*[e.cuda_event for e in self.events])
+        self.timed = [i for i, n in enumerate(self.names) if only is None or n in only]
+        self.events = [None] * (2 * len(self.names))
+        for i in self.timed:
+            for k in (2 * i, 2 * i + 1):
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(self.stream)          # torch creates the HIP event on first record
+                self.events[k] = e
+        self.handles = (ctypes.c_void_p * len(self.events))(
+            *[e.cuda_event if e is not None else None for e in self.events])
+
+    def _sync(self):
+        for e in self.events:
+            if e is not None:
+                e.synchronize()
 
     def ms(self):
-        """Per-stage device milliseconds of the last staged sort (waits for it)."""
-        for e in self.events:
-            e.synchronize()
-        return {n: self.events[2 * i].elapsed_time(self.events[2 * i + 1])
-                for i, n in enumerate(self.names)}
+        """Per-stage device milliseconds of the last staged sort (waits for
+        it), for the timed stages."""
+        self._sync()
+        return {self.names[i]: self.events[2 * i].elapsed_time(self.events[2 * i + 1])
+                for i in self.timed}
 
     def span_ms(self, pick):
         """Milliseconds from the earliest start to the latest end of the
-        stages whose names satisfy pick (stages may overlap)."""
-        idx = [i for i, n in enumerate(self.names) if pick(n)]
+        timed stages whose names satisfy pick (stages may overlap)."""
+        idx = [i for i in self.timed if pick(self.names[i])]
         if not idx:
             return 0.0
-        ref = self.events[0]
-        ref.synchronize()
-        for e in self.events:
-            e.synchronize()
+        self._sync()
+        ref = self.events[2 * self.timed[0]]
         t0 = min(ref.elapsed_time(self.events[2 * i]) for i in idx)
         t1 = max(ref.elapsed_time(self.events[2 * i + 1]) for i in idx)
         return t1 - t0

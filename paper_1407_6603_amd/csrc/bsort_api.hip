@@ -581,7 +581,7 @@ static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, h
 static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
                                void* const* ev, const int32_t* d_pmax) {
     auto rec = [&](int i, int end, hipStream_t x) -> hipError_t {
-        return ev ? hipEventRecord((hipEvent_t)ev[2 * i + end], x) : hipSuccess;
+        return ev && ev[2 * i + end] ? hipEventRecord((hipEvent_t)ev[2 * i + end], x) : hipSuccess;
     };
     hipError_t e = hipSuccess;
     if (bucketize) {
@@ -668,8 +668,6 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
     if (events) {
         if (n_events != 2 * bsort_stage_count(b->max_len))
             return fail(BSORT_E_INVALID, "n_events must be 2 * bsort_stage_count(max_len)");
-        for (int i = 0; i < n_events; ++i)
-            if (!events[i]) return fail(BSORT_E_INVALID, "an event is NULL");
         if (t && (t->flags & BSORT_FLAG_PER_BUCKET_LAUNCH))
             return fail(BSORT_E_INVALID, "the per-bucket form cannot be staged");
     }

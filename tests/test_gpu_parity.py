@@ -442,3 +442,24 @@ def test_staged_batch_equals_unstaged(bs, ws, batch_small):
     assert all(v >= 0 for v in ms.values())
     assert np.array_equal(perm.cpu().numpy(), gpu_batch(bs, ws, sub, 12))
 
+
+
+def test_staged_batch_times_only_chosen_stages(bs, ws, batch_small):
+    """NULL entries of the event array record nothing: a timer of two stages
+    reports those two, and the bits do not change."""
+    sub = wordgen.Batch.concat([batch_small.request(r) for r in range(100)])
+    b, o = bs.to_device(sub.bytes, sub.offsets)
+    rs = torch.from_numpy(sub.req_start).cuda()
+    pick = {"bucketize", "lds_d2_1024"}
+    timer = bs.StageTimer(12, only=pick)
+    assert sum(h is not None for h in timer.handles) == 2 * len(pick)
+    perm = bs.sort_batch_staged(b, o, rs, sub.req_start, 12, timer, ws=ws)
+    ms = timer.ms()
+    bs.check_device_status(ws)
+    assert set(ms) == pick and all(v >= 0 for v in ms.values())
+    none = bs.StageTimer(12, only=())
+    perm2 = bs.sort_batch_staged(b, o, rs, sub.req_start, 12, none, ws=ws)
+    assert none.ms() == {}
+    ref = gpu_batch(bs, ws, sub, 12)
+    assert np.array_equal(perm.cpu().numpy(), ref)
+    assert np.array_equal(perm2.cpu().numpy(), ref)
