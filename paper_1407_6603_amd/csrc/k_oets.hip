@@ -693,8 +693,11 @@ __device__ void lds_merge_phase_waves(uint32_t* lds, int n, int T, int logT, int
         const int e = (m + kWave - 1) / kWave;            // per lane, <= kWaveRunMax
         const int diag = lane * e;
         const int cnt = m - diag < e ? (m - diag > 0 ? m - diag : 0) : e;
+        // a merge-path search range never exceeds the shorter side (>= 1
+        // here): bit_length of it rounds suffice
+        const int logw = 31 - __builtin_clz((unsigned)(na < j1 ? na : j1));
         uint32_t out[kWaveRunMax][D];
-        if (cnt > 0) lds_merge_slot<D, kWaveRunMax, FULL>(lds, CAP, n, wlo, na, logT, j1, diag,
+        if (cnt > 0) lds_merge_slot<D, kWaveRunMax, FULL>(lds, CAP, n, wlo, na, logw, j1, diag,
                                                            out, e);
 #pragma unroll
         for (int j = 0; j < kWaveRunMax; ++j) {
