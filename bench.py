@@ -28,7 +28,9 @@ if ROOT not in sys.path:
 
 import wordgen  # noqa: E402
 
-PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12     # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T ops/s
+# 32-bit VALU peak from the fp32 vector figure (157.3 TFLOP/s = 78.6 T FMA
+# lanes/s): 256 CUs x 128 lanes/clk x 2.4 GHz
+PEAK_INT32_TOPS = 256 * 128 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 128 B/clk/CU LDS bandwidth: 78.6 TB/s
 
@@ -725,12 +727,6 @@ def main():
                 "launch_ms": dom_ms, "launch_ms_alone": alone.get(dom),
                 "ce_per_launch": ce,
                 "ce_per_s": ce / sec, "ops_per_ce": 3 * D, "words_per_launch": w["words"]}
-        # the compare-exchange roofline as an LDS stream: each CE reads and
-        # writes two (key, index) records, 4 * 4D bytes
-        lds_ce = 16 * D * ce
-        roof["lds_ce"] = {"bytes_per_ce": 16 * D, "bytes": lds_ce,
-                          "achieved_tb_s": lds_ce / sec / 1e12, "peak_tb_s": PEAK_LDS_TBS,
-                          "frac": lds_ce / sec / 1e12 / PEAK_LDS_TBS}
         if "lds_bytes" in w:
             roof["merge_lds_bytes"] = w["lds_bytes"]
             roof["floor_ms"] = (ops / (PEAK_INT32_TOPS * 1e12)

@@ -317,7 +317,8 @@ __device__ __forceinline__ void push_item(const Job* J, int s1, const MergeItem&
         set_status(J, ST_OVERFLOW);
         return;
     }
-    const int slot = atomicAdd(&J->mcount[s1], 1);
+    const int slot = __hip_atomic_fetch_add(gp(J->mcount) + s1, 1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
     if (slot < J->merge_cap) J->mlist[s1 & 1][slot] = m;
     else set_status(J, ST_OVERFLOW);
 }

@@ -36,6 +36,11 @@ __global__ __launch_bounds__(256) void k_sort_init(const Job* __restrict__ J) {
 
 // one wave per list; the workgroup's four waves share one global claim per
 // record width D and one for the first merge phase
+// device-scope add on a global counter, returning the old value
+__device__ __forceinline__ int gadd(int32_t* p, int v) {
+    return __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
     __shared__ int64_t kos[kTileWavesPerBlock][kMaxLen + 1];
     __shared__ int blk_tiles[kNumD];
@@ -112,20 +117,21 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
                 else tslot[k] = atomicAdd(&blk_tiles[D], nt[k]);
                 if (nt[k] >= 2 && !tiles_only) {
                     islot[k] = atomicAdd(&blk_items, nt[k] / 2);
-                    atomicMax(J->pmax, nt[k]);
+                    __hip_atomic_fetch_max(gp(J->pmax), nt[k], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
         }
     }
     __syncthreads();
     if (tid < kNumD && blk_tiles[tid] > 0)
-        blk_tile_base[tid] = atomicAdd(&J->tile_count[tid], blk_tiles[tid]);
-    if (tid == kNumD && blk_items > 0) blk_item_base = atomicAdd(&J->mcount[0], blk_items);
+        blk_tile_base[tid] = gadd(J->tile_count + tid, blk_tiles[tid]);
+    if (tid == kNumD && blk_items > 0) blk_item_base = gadd(J->mcount, blk_items);
     if (tid < 2 * kLb && blk_lb[tid] > 0)
-        blk_lb_base[tid] = atomicAdd(tid < kLb ? &J->lb_count[tid] : &J->lb_back[tid - kLb],
-                                     blk_lb[tid]);
+        blk_lb_base[tid] = gadd(tid < kLb ? J->lb_count + tid : J->lb_back + (tid - kLb),
+                                blk_lb[tid]);
     if (tid <= kLdsMaxD && blk_hc[tid] > 0)
-        blk_hc_base[tid] = atomicAdd(&J->hc_count[tid], blk_hc[tid]);
+        blk_hc_base[tid] = gadd(J->hc_count + tid, blk_hc[tid]);
     __syncthreads();
     if (!active) return;
 
