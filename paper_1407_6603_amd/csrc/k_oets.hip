@@ -343,9 +343,9 @@ __device__ __forceinline__ void sort_tile_any(const Src& src, int n, int lane) {
 // Two-dword records compared whole (key dwords of a 5- or 6-byte word, its
 // position in the sub-array in the low 16 bits of the second, which the key
 // leaves zero): the exact fp64 form when the wave's records allow it, else
-// the three-dword integer tile sort, whose key is exactly these two dwords
-// (the third plane is carried along unused).  Padding records (all ones)
-// sort last.
+// the three-dword integer phases, whose key is exactly these two dwords (with
+// a zero third dword in registers: the index plane in LDS stays as loaded).
+// Padding records (all ones) sort last.
 template <int K, class Src>
 __device__ __forceinline__ void sort_tile_full2(const Src& src, int n, int lane) {
     uint32_t r[K][2];
@@ -356,9 +356,81 @@ __device__ __forceinline__ void sort_tile_full2(const Src& src, int n, int lane)
         if (lane * K + k < n && (r[k][0] >= kF64KeyLimit || r[k][1] >= 0x80000000u)) ok = false;
     if (__all(ok)) {
         phases_f64<K>(r, n);
-        src.template store<2, K>(r, lane);
     } else {
-        sort_tile<3, K>(src, n, lane);
+        uint32_t r3[K][3];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            r3[k][0] = r[k][0];
+            r3[k][1] = r[k][1];
+            r3[k][2] = 0u;
+        }
+        phases_int<3, K>(r3, n);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            r[k][0] = r3[k][0];
+            r[k][1] = r3[k][1];
+        }
+    }
+    src.template store<2, K>(r, lane);
+}
+
+// One-dword records (a 1- or 2-byte word's key in the high half, its
+// position in the sub-array in the low half, which the key leaves zero),
+// compared whole: a compare-exchange is one v_min_u32 and one v_max_u32.
+// All-ones pads the tile and sorts last; the edge lanes' neighbours are
+// all-ones (right) and zero (left), so they never exchange.
+template <int K>
+__device__ __forceinline__ void phases_u32(uint32_t (&x)[K], int n) {
+    const int nph = __builtin_amdgcn_readfirstlane(n);
+    uint32_t rf = 0xFFFFFFFFu, ll = 0u;
+    int ph = 0;
+    for (; ph + 2 <= nph; ph += 2) {
+#pragma unroll
+        for (int k = 0; k + 1 < K; k += 2) {
+            const uint32_t lo = x[k] < x[k + 1] ? x[k] : x[k + 1];
+            const uint32_t hi = x[k] < x[k + 1] ? x[k + 1] : x[k];
+            x[k] = lo;
+            x[k + 1] = hi;
+        }
+        rf = (uint32_t)__builtin_amdgcn_update_dpp((int)rf, (int)x[0], kDppWaveShl1, 0xF, 0xF,
+                                                   false);
+        ll = (uint32_t)__builtin_amdgcn_update_dpp((int)ll, (int)x[K - 1], kDppWaveShr1, 0xF,
+                                                   0xF, false);
+#pragma unroll
+        for (int k = 1; k + 1 <= K - 2; k += 2) {
+            const uint32_t lo = x[k] < x[k + 1] ? x[k] : x[k + 1];
+            const uint32_t hi = x[k] < x[k + 1] ? x[k + 1] : x[k];
+            x[k] = lo;
+            x[k + 1] = hi;
+        }
+        x[K - 1] = x[K - 1] < rf ? x[K - 1] : rf;
+        x[0] = ll < x[0] ? x[0] : ll;
+    }
+    if (ph < nph) {
+#pragma unroll
+        for (int k = 0; k + 1 < K; k += 2) {
+            const uint32_t lo = x[k] < x[k + 1] ? x[k] : x[k + 1];
+            const uint32_t hi = x[k] < x[k + 1] ? x[k + 1] : x[k];
+            x[k] = lo;
+            x[k + 1] = hi;
+        }
+    }
+}
+
+template <int K, int KCAP, class Src>
+__device__ __forceinline__ void sort_tile_full1_k(const Src& src, int n, int lane, int kneed) {
+    if (K * 2 > KCAP || kneed <= K) {
+        uint32_t r[K][1];
+        src.template load<1, K>(r, lane);
+        uint32_t x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = r[k][0];
+        phases_u32<K>(x, n);
+#pragma unroll
+        for (int k = 0; k < K; ++k) r[k][0] = x[k];
+        src.template store<1, K>(r, lane);
+    } else if constexpr (K * 2 <= KCAP) {
+        sort_tile_full1_k<K * 2, KCAP>(src, n, lane, kneed);
     }
 }
 
@@ -780,19 +852,22 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         const gptr<int32_t> perm = gp(J->perm) + bk.pos0;
         // 5- and 6-byte words whose keys are not written back: a record is
         // the two key dwords with the word's position (n <= CAP < 2^16) in
-        // the zero low half of the second, compared whole; the index comes
-        // from the position at the end
+        // the zero low half of the second, compared whole; the index plane
+        // keeps input order and is read at that position at the end
         const bool full2 = D == 3 && bk.L <= 6 && !bk.wk;    // uniform
+        // 1- and 2-byte words likewise: one dword, the key's high half and
+        // the position (n <= CAP <= 2^16) in the zero low half
+        const bool full1 = D == 2 && bk.L <= 2 && !bk.wk;    // uniform
 #pragma unroll 4
         for (int i = tid; i < n; i += NT) {
             const int a = lsw(i);
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 const uint64_t v = keys[w * ks + i];
-                lds[(2 * w) * CAP + a] = (uint32_t)(v >> 32);
+                lds[(2 * w) * CAP + a] = (uint32_t)(v >> 32) | (full1 ? i : 0);
                 if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + a] = (uint32_t)v | (full2 ? i : 0);
             }
-            if (!full2) lds[Dk * CAP + a] = (uint32_t)perm[i];
+            lds[Dk * CAP + a] = (uint32_t)perm[i];     // index plane (unused by full1/2 sorts)
         }
         __syncthreads();
         const int p = (n + T - 1) / T;
@@ -806,20 +881,33 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
                     continue;
                 }
             }
+            if constexpr (D == 2) {
+                if (full1) {
+                    sort_tile_full1_k<2, KCAP>(src, tn, lane, (tn + kWave - 1) / kWave);
+                    continue;
+                }
+            }
             sort_tile_any<D, KCAP>(src, tn, lane);
         }
         __syncthreads();
         if constexpr (D == 3) {
             if (full2) {
                 if (!tiles_only) lds_merge_all<2, NT, CAP, true>(lds, n, T, logT, p, tid, mwin);
-                // each output's index from its position, gathered into the
-                // free third plane before any is written over
-                for (int i = tid; i < n; i += NT) {
-                    const int a = lsw(i);
-                    lds[2 * CAP + a] = (uint32_t)perm[(int)(lds[CAP + a] & 0xFFFFu)];
-                }
-                __syncthreads();
-                for (int i = tid; i < n; i += NT) perm[i] = (int32_t)lds[2 * CAP + lsw(i)];
+                // each output's index from the index plane, at the position
+                // the record carries (that plane is never written while sorting)
+                for (int i = tid; i < n; i += NT)
+                    perm[i] = (int32_t)lds[2 * CAP + lsw((int)(lds[CAP + lsw(i)] & 0xFFFFu))];
+                __syncthreads();                       // LDS reused by the next sub-array
+                continue;
+            }
+        }
+        if constexpr (D == 2) {
+            if (full1) {
+                if (!tiles_only) lds_merge_all<1, NT, CAP, true>(lds, n, T, logT, p, tid, mwin);
+                // each output's index from the index plane, at the position
+                // the record carries (that plane is never written while sorting)
+                for (int i = tid; i < n; i += NT)
+                    perm[i] = (int32_t)lds[CAP + lsw((int)(lds[lsw(i)] & 0xFFFFu))];
                 __syncthreads();                       // LDS reused by the next sub-array
                 continue;
             }
