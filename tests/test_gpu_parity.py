@@ -339,6 +339,30 @@ def test_one_two_byte_words_in_every_class(bs, ws, alphabet):
         assert np.array_equal(got, expect), T
 
 
+@pytest.mark.parametrize("alphabet", [b"eatonsEAT", None, b"\x00\x01\x7f\x80\xfe\xff"])
+def test_nine_ten_byte_words_in_every_class(bs, ws, alphabet):
+    """9- and 10-byte words (four-dword records, the last key dword half
+    padding): letters, all byte values, the extreme bytes, heavy duplicates,
+    sizes at every four-dword size class and past the largest (merged
+    through HBM)."""
+    rng = np.random.default_rng(910)
+    lists = []
+    for cap in lds_caps(4) + [9216 + 129]:
+        for L in (9, 10):
+            for n in (cap - 1, cap // 2 + 3):
+                if alphabet is None:
+                    w = wordgen.random_words(rng, n, L, L)
+                else:
+                    pool = wordgen.random_words(rng, 40, L, L, alphabet=alphabet).as_list()
+                    w = wordgen.Words.from_list([pool[i] for i in rng.integers(0, 40, n)])
+                lists.append(w)
+    batch = wordgen.Batch.concat(lists)
+    expect = oracle.definition_sort_batch(batch.bytes, batch.offsets, batch.req_start, 16)
+    for T in (128, 512):
+        got = gpu_batch(bs, ws, batch, 10, tune=bs.tuning(T, 0))
+        assert np.array_equal(got, expect), T
+
+
 def test_large_serve_request_merged_through_hbm(bs, ws):
     """A 1,000,000-word request of the serving workload (lengths to 32, one
     200,000-word vocabulary): its large sub-arrays are cut into chunks sorted
