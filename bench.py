@@ -42,15 +42,15 @@ PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 128 B/clk/CU LDS bandwidth: 78.6
 SORT_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TOK_SOURCES = ("paper_1407_6603_amd/csrc/k_tokenize.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TRAFFIC = {
-    "k_bucket_lds<2, 1024, 16384>": {"read": 66544102, "write": 22090168,
-                                     "files": SORT_SOURCES, "sources": "dfab35369f794803"},
-    "k_bucket_lds<3, 1024, 8192>": {"read": 38650388, "write": 12720224,
-                                    "files": SORT_SOURCES, "sources": "dfab35369f794803"},
-    "k_tok_count": {"read": 189679119, "write": 743856,
+    "k_bucket_lds<2, 1024, 16384>": {"read": 66676313, "write": 22090544,
+                                     "files": SORT_SOURCES, "sources": "de97d6ba28aee748"},
+    "k_bucket_lds<3, 1024, 8192>": {"read": 38576947, "write": 12720496,
+                                    "files": SORT_SOURCES, "sources": "de97d6ba28aee748"},
+    "k_tok_count": {"read": 189694648, "write": 746176,
                     "files": TOK_SOURCES, "sources": "bd221f5c20dd1065"},
     "k_tok_scan": {"read": 110204, "write": 183712,
                    "files": TOK_SOURCES, "sources": "bd221f5c20dd1065"},
-    "k_tok_write": {"read": 191130903, "write": 403941472,
+    "k_tok_write": {"read": 191128385, "write": 403947040,
                     "files": TOK_SOURCES, "sources": "bd221f5c20dd1065"},
 }
 
