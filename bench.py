@@ -745,7 +745,7 @@ def main():
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                 "traffic": None, "bytes_per_step": merge_bytes}
 
-    # ---- CPU baseline: the oracle (paper's procedure) on a strided sample
+    # ---- CPU baseline: the oracle (paper's procedure) on the batch (or every k-th list)
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
