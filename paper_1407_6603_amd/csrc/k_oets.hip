@@ -1137,7 +1137,13 @@ int pair_merge_lds(int dmax) {
 
 hipError_t launch_merge_pairs(const Job* J, const Bounds& b, int phase, hipStream_t s) {
     const int64_t cap = (b.total / kMinTile + (int64_t)b.R * b.ml1) / 2 + 1;
-    const int64_t g = cap < 1024 ? cap : 1024;
+    // as many workgroups as stay resident (their LDS decides): they stride
+    // over the phase's items, and a phase with none (captured plans launch
+    // every phase up to the bound) costs one round of empty workgroups
+    int64_t per_cu = (160 * 1024) / ((int64_t)b.pair_lds + 4 * (kMergeWinWords + 1));
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 4) per_cu = 4;
+    const int64_t g = cap < 256 * per_cu ? cap : 256 * per_cu;
     k_merge_pairs<<<(unsigned)(g < 1 ? 1 : g), kPairThreads, b.pair_lds, s>>>(J, phase);
     return hipGetLastError();
 }
