@@ -65,7 +65,7 @@ enum : uint32_t {
 // lds_cap(c, D) words in LDS (D dwords per word, at most 144 KiB) and sorts
 // it there.  Size classes c = 0..4; the largest class is sized per width D.
 constexpr int kLdsClasses = 5;
-constexpr int kLdsMaxD = 5;
+constexpr int kLdsMaxD = 9;
 constexpr int kLdsBytes = 144 * 1024;
 __host__ __device__ constexpr int lds_cap(int c, int D) {
     return c < 4 ? (1024 << c) : (D <= 2 ? 16384 : D == 3 ? 12288 : D == 4 ? 9216 : 7168);
@@ -110,7 +110,7 @@ __host__ __device__ constexpr int lds_tile(int tuned, int cap, int D) {
 // host).  hbm_pair_cap(D) = 2C is the pair merge's LDS capacity in records.
 __host__ __device__ constexpr int hbm_chunk_max(int D) {
     int c = 8192;
-    while (c > 128 && 2 * c * 4 * D > kLdsBytes) c >>= 1;
+    while (c > 128 && 2 * c * 4 * D > kLdsBytes - 2048) c >>= 1;   // (room for the window table)
     return c;
 }
 // in-LDS class that sorts chunks of up to C words of width D (-1: none)

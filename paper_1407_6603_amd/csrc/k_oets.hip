@@ -986,7 +986,8 @@ using LdsLauncher = void (*)(const Job*, int64_t, int, hipStream_t);
     {launch_lds_class_t<D, 0>, launch_lds_class_t<D, 1>, launch_lds_class_t<D, 2>, \
      launch_lds_class_t<D, 3>, launch_lds_class_t<D, 4>}
 static const LdsLauncher kLdsLaunchers[kLdsMaxD + 1][kLdsClasses] = {
-    {}, {}, BSORT_LDS_ROW(2), BSORT_LDS_ROW(3), BSORT_LDS_ROW(4), BSORT_LDS_ROW(5)};
+    {}, {}, BSORT_LDS_ROW(2), BSORT_LDS_ROW(3), BSORT_LDS_ROW(4), BSORT_LDS_ROW(5),
+    BSORT_LDS_ROW(6), BSORT_LDS_ROW(7), BSORT_LDS_ROW(8), BSORT_LDS_ROW(9)};
 #undef BSORT_LDS_ROW
 
 hipError_t launch_lds_class(const Job* J, const Bounds& b, int D, int c, hipStream_t s) {
