@@ -91,11 +91,12 @@ def kmax_for(D):
 
 
 LDS_BYTES = 144 * 1024
+LDS_MAX_D = 9                     # widest record with in-LDS classes
 
 
 def lds_caps_for(D):
     """Capacities of the in-LDS size classes for record width D (empty: none)."""
-    if not 2 <= D <= 5:
+    if not 2 <= D <= LDS_MAX_D:
         return []
     top = 16384 if D <= 2 else 12288 if D == 3 else 9216 if D == 4 else 7168
     caps = [1024 << c for c in range(4)] + [top]
@@ -115,7 +116,7 @@ def hbm_chunk(D):
     """Tile of sub-arrays merged through HBM for record widths with in-LDS
     classes: the largest power of two whose pair of tiles fits 144 KiB."""
     c = 8192
-    while c > 128 and 2 * c * 4 * D > LDS_BYTES:
+    while c > 128 and 2 * c * 4 * D > LDS_BYTES - 2048:   # room for the window table
         c >>= 1
     return c
 
@@ -148,7 +149,7 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
         D = (L + 3) // 4 + 1
         W = (L + 7) // 8
         T = min(tile_keys, 64 * kmax_for(D), 1024)
-        Th = hbm_chunk(D) if D <= 5 else min(hbm_tile_keys, 64 * kmax_for(D))
+        Th = hbm_chunk(D) if D <= LDS_MAX_D else min(hbm_tile_keys, 64 * kmax_for(D))
         caps = lds_caps_for(D)
         cap = max(caps) if caps else 0
         n = counts[:, L].astype(np.int64)

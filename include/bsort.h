@@ -162,7 +162,7 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
  * (tile planning), one "tiles_d<D>" tile-sort launch per record
  * width D = 2 .. ceil(max_len/4)+1 (D = ceil(L/4)+1 for words of L bytes),
  * one "lds_d<D>_<C>" launch per in-LDS size class of capacity C words for
- * D = 2 .. min(5, ceil(max_len/4)+1) (sub-arrays sorted whole in LDS; C =
+ * D = 2 .. min(9, ceil(max_len/4)+1) (sub-arrays sorted whole in LDS; C =
  * 1024, 2048, 4096, 8192 where D*4*C <= 144 KiB, and a largest class of
  * 16384, 12288, 9216 or 7168 words for D = 2, 3, 4, 5), and "merge_split"
  * (phases through HBM).  bsort_stage_count(max_len) is their number and

@@ -414,7 +414,7 @@ static Job batch_job(const Layout& L, char* ws, const Bounds& bd, const bsort_ba
 }
 
 // stages: bucketize, pack, tiles_d2..tiles_d<dmax>, then one stage per in-LDS
-// size class, lds_d<D>_<capacity> for D = 2..min(5, dmax), then merge_split
+// size class, lds_d<D>_<capacity> for D = 2..min(9, dmax), then merge_split
 static int stage_dmax(int32_t max_len) { return max_len >= 1 ? dwords_for_len(max_len) : 1; }
 static int stage_lds_max(int32_t max_len) { return std::min(stage_dmax(max_len), kLdsMaxD); }
 
