@@ -42,16 +42,16 @@ PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 128 B/clk/CU LDS bandwidth: 78.6
 SORT_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TOK_SOURCES = ("paper_1407_6603_amd/csrc/k_tokenize.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TRAFFIC = {
-    "k_bucket_lds<2, 1024, 16384>": {"read": 66674681, "write": 22090048,
-                                     "files": SORT_SOURCES, "sources": "cd372004910c5879"},
-    "k_bucket_lds<3, 1024, 8192>": {"read": 38583218, "write": 12720776,
-                                    "files": SORT_SOURCES, "sources": "cd372004910c5879"},
-    "k_tok_count": {"read": 189681976, "write": 743456,
-                    "files": TOK_SOURCES, "sources": "bd221f5c20dd1065"},
+    "k_bucket_lds<2, 1024, 16384>": {"read": 66702144, "write": 22090472,
+                                     "files": SORT_SOURCES, "sources": "01157a2813442cec"},
+    "k_bucket_lds<3, 1024, 8192>": {"read": 38605206, "write": 12720696,
+                                    "files": SORT_SOURCES, "sources": "01157a2813442cec"},
+    "k_tok_count": {"read": 189662544, "write": 740160,
+                    "files": TOK_SOURCES, "sources": "e923714993a4c7e1"},
     "k_tok_scan": {"read": 110204, "write": 183712,
-                   "files": TOK_SOURCES, "sources": "bd221f5c20dd1065"},
-    "k_tok_write": {"read": 191130625, "write": 403947360,
-                    "files": TOK_SOURCES, "sources": "bd221f5c20dd1065"},
+                   "files": TOK_SOURCES, "sources": "e923714993a4c7e1"},
+    "k_tok_write": {"read": 191129687, "write": 403946576,
+                    "files": TOK_SOURCES, "sources": "e923714993a4c7e1"},
 }
 
 
