@@ -253,8 +253,8 @@ def test_zero_one_merge_seams(bs, ws, T):
 
 def lds_caps(D):
     """In-LDS size-class capacities for record width D (largest class per
-    width within 144 KiB of LDS)."""
-    top = {2: 16384, 3: 12288, 4: 9216, 5: 7168}[D]
+    width within 144 KiB of LDS; widths 6-9 have the classes up to 4,096)."""
+    top = {2: 16384, 3: 12288, 4: 9216, 5: 7168}.get(D, 8192)
     return [c for c in (1024, 2048, 4096, 8192, top) if D * 4 * c <= 144 * 1024]
 
 
@@ -266,9 +266,9 @@ def lds_tile(tuned, cap, D):
     return t
 
 
-@pytest.mark.parametrize("L", [1, 5, 9, 13])
+@pytest.mark.parametrize("L", [1, 5, 9, 13, 17, 21, 25, 29])
 def test_zero_one_lds_classes(bs, ws, L):
-    """0/1 keys of width L (record widths D = 2..5) at the bounds of every
+    """0/1 keys of width L (record widths D = 2..9) at the bounds of every
     in-LDS size class, one class tile past each lower bound, and past the
     largest class (merge-split through HBM): the stable partition."""
     T = 128
@@ -360,6 +360,35 @@ def test_nine_ten_byte_words_in_every_class(bs, ws, alphabet):
     expect = oracle.definition_sort_batch(batch.bytes, batch.offsets, batch.req_start, 16)
     for T in (128, 512):
         got = gpu_batch(bs, ws, batch, 10, tune=bs.tuning(T, 0))
+        assert np.array_equal(got, expect), T
+
+
+@pytest.mark.parametrize("alphabet", [b"eatonsEAT", None, b"\x00\x01\x7f\x80\xfe\xff", "prefix"])
+def test_long_words_in_every_class(bs, ws, alphabet):
+    """17- to 32-byte words (records of 6-9 dwords, whose in-LDS classes hold
+    up to 4,096 words): letters, all byte values, the extreme bytes, and
+    words that share all but their last two bytes (every key dword but the
+    last ties), heavy duplicates, sizes at every class and past the largest
+    (merged through HBM)."""
+    rng = np.random.default_rng(1732)
+    lists = []
+    for cap in lds_caps(6) + [4096 + 129]:
+        for L in (17, 24, 25, 32):
+            for n in (cap - 1, cap // 2 + 3):
+                if alphabet is None:
+                    w = wordgen.random_words(rng, n, L, L)
+                elif alphabet == "prefix":
+                    head = bytes(rng.integers(97, 123, L - 2, dtype=np.uint8))
+                    tails = rng.integers(0, 256, (n, 2), dtype=np.uint8)
+                    w = wordgen.Words.from_list([head + bytes(t) for t in tails])
+                else:
+                    pool = wordgen.random_words(rng, 40, L, L, alphabet=alphabet).as_list()
+                    w = wordgen.Words.from_list([pool[i] for i in rng.integers(0, 40, n)])
+                lists.append(w)
+    batch = wordgen.Batch.concat(lists)
+    expect = oracle.definition_sort_batch(batch.bytes, batch.offsets, batch.req_start, 16)
+    for T in (128, 512):
+        got = gpu_batch(bs, ws, batch, 32, tune=bs.tuning(T, 0))
         assert np.array_equal(got, expect), T
 
 
