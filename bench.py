@@ -5,10 +5,15 @@ Default workload: the batching workload -- 4,096 independent word lists with
 sizes log-uniform in [16, 65,536] (~31.8 M words), each drawn like the small
 single-list workload (800-word seeded vocabulary, lengths 1-12, Zipf 1.1,
 5% capitalised).  A step sorts the whole batch: bucketize, key pack, tile
-odd-even transposition sort and block merge-split, all lists in one captured
-graph launch.  Inputs are device-resident before timing starts.
+odd-even transposition sort and block merge-split for all lists, as one
+batched call (a few launches per stage, not one per list); the same batch
+through one captured graph launch is timed beside it.  Inputs are
+device-resident before timing starts.
 
-Prints one JSON line.  See the design doc for the roofline definitions.
+Prints one JSON line.  The roofline object prices the longest kernel of the
+step: its algorithmic compare-exchange lane operations per launch (3 per
+record dword per compare-exchange) over its measured launch time, against
+the 32-bit vector ALU peak (256 CUs x 128 lanes/clock x 2.4 GHz).
 """
 from __future__ import annotations
 
@@ -404,7 +409,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by list across GPUs, see DESIGN.md)", file=sys.stderr)
+              "(lists are independent: several GPUs would shard whole lists by size)",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
