@@ -489,6 +489,8 @@ struct FanPool {
     hipStream_t aux[kFan - 1] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kFan - 1] = {};
+    hipEvent_t prep_fork = nullptr;  // the plan beside the scatter, on aux[0]
+    hipEvent_t prep_join = nullptr;
     hipEvent_t pmax_ev = nullptr;   // the merge-split phase count has reached the host
     int32_t* host_pmax = nullptr;   // pinned
 };
@@ -520,6 +522,8 @@ static hipError_t fan_init_readback(FanPool& f) {
 static hipError_t fan_init(FanPool& f) {
     if (f.ready) return fan_init_readback(f);
     hipError_t e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f.prep_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f.prep_join, hipEventDisableTiming);
     for (int k = 0; k < kFan - 1 && e == hipSuccess; ++k) {
         e = hipStreamCreateWithFlags(&f.aux[k], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.join[k], hipEventDisableTiming);
@@ -570,8 +574,11 @@ static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, h
     }
 }
 
-// Everything after the job descriptor: bucketize (if asked), prep and pack on
-// the caller's stream, then the sort stages fanned out and joined back.
+// Everything after the job descriptor: bucketize (if asked), prep and pack,
+// then the sort stages fanned out and joined back.  With the library streams
+// and a bucketize pass, the plan (which needs only counts and starts) runs on
+// a library stream beside the scatter; otherwise everything before the sort
+// stages is on the caller's stream.
 // ev (optional): 2 events per stage in bsort_stage_name order, recorded just
 // before and after the stage on the stream that runs it.  d_pmax (optional):
 // the job's device word holding the most merge-split phases any sub-array
@@ -584,17 +591,9 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
         return ev && ev[2 * i + end] ? hipEventRecord((hipEvent_t)ev[2 * i + end], x) : hipSuccess;
     };
     hipError_t e = hipSuccess;
-    if (bucketize) {
-        if ((e = rec(0, 0, s)) != hipSuccess) return e;
-        if ((e = launch_bucketize(J, b, s)) != hipSuccess) return e;
-        if ((e = rec(0, 1, s)) != hipSuccess) return e;
-    }
-    if ((e = rec(1, 0, s)) != hipSuccess) return e;
-    if ((e = launch_sort_prep(J, b, s)) != hipSuccess) return e;
-    if ((e = rec(1, 1, s)) != hipSuccess) return e;
-
     // BSORT_FLAG_SERIAL_STAGES: every stage on s and no library stream
     const bool fan = !(b.flags & BSORT_FLAG_SERIAL_STAGES);
+    const bool prep_beside = fan && bucketize && b.fused_pack;
     bool readback = false;
     if (d_pmax && b.phase_bound > 4 && !(b.flags & kFlagTilesOnly)) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -609,6 +608,27 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     if (fan || readback) {
         lock.lock();
         if ((e = fan ? fan_init(f) : fan_init_readback(f)) != hipSuccess) return e;
+    }
+    if (bucketize) {
+        if ((e = rec(0, 0, s)) != hipSuccess) return e;
+        if ((e = launch_bucket_starts(J, b, s)) != hipSuccess) return e;
+        if (prep_beside) {
+            hipStream_t x = f.aux[0];
+            if ((e = hipEventRecord(f.prep_fork, s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(x, f.prep_fork, 0)) != hipSuccess) return e;
+            if ((e = rec(1, 0, x)) != hipSuccess) return e;
+            if ((e = launch_sort_prep(J, b, true, x)) != hipSuccess) return e;
+            if ((e = rec(1, 1, x)) != hipSuccess) return e;
+            if ((e = hipEventRecord(f.prep_join, x)) != hipSuccess) return e;
+        }
+        if ((e = launch_scatter(J, b, s)) != hipSuccess) return e;
+        if ((e = rec(0, 1, s)) != hipSuccess) return e;
+        if (prep_beside && (e = hipStreamWaitEvent(s, f.prep_join, 0)) != hipSuccess) return e;
+    }
+    if (!prep_beside) {
+        if ((e = rec(1, 0, s)) != hipSuccess) return e;
+        if ((e = launch_sort_prep(J, b, bucketize, s)) != hipSuccess) return e;
+        if ((e = rec(1, 1, s)) != hipSuccess) return e;
     }
     if (readback) {
         if ((e = hipMemcpyAsync(f.host_pmax, d_pmax, sizeof(int32_t), hipMemcpyDeviceToHost,

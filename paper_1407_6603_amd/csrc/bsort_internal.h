@@ -347,8 +347,12 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
 
 hipError_t launch_set_job(const Job& j, Job* dst, hipStream_t s);
 hipError_t launch_bucketize(const Job* J, const Bounds& b, hipStream_t s);
+// the two halves of launch_bucketize: counts, starts and key offsets; then the scatter
+hipError_t launch_bucket_starts(const Job* J, const Bounds& b, hipStream_t s);
+hipError_t launch_scatter(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_chunk_plan(const Job* J, const Bounds& b, bool clear_status, hipStream_t s);
-hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s);
+// after_bucketize: launch_bucket_starts of this call wrote key_off already
+hipError_t launch_sort_prep(const Job* J, const Bounds& b, bool after_bucketize, hipStream_t s);
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_class(const Job* J, const Bounds& b, int D, int c, hipStream_t s);

@@ -374,14 +374,23 @@ hipError_t launch_chunk_plan(const Job* J, const Bounds& b, bool clear_status, h
     return hipGetLastError();
 }
 
-hipError_t launch_bucketize(const Job* J, const Bounds& b, hipStream_t s) {
+hipError_t launch_bucket_starts(const Job* J, const Bounds& b, hipStream_t s) {
     hipError_t e = launch_chunk_plan(J, b, true, s);
     if (e != hipSuccess) return e;
     k_chunk_hist<<<grid_for(b.chunk_cap, kTileWavesPerBlock), 256, 0, s>>>(J);
     k_chunk_scan<<<grid_for((int64_t)b.R * b.ml1, kTileWavesPerBlock), 256, 0, s>>>(J);
     k_bucket_starts<<<grid_for(b.R, kTileWavesPerBlock), 256, 0, s>>>(J);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Job* J, const Bounds& b, hipStream_t s) {
     k_scatter<<<grid_for(b.chunk_cap, kTileWavesPerBlock), 256, 0, s>>>(J);
     return hipGetLastError();
+}
+
+hipError_t launch_bucketize(const Job* J, const Bounds& b, hipStream_t s) {
+    hipError_t e = launch_bucket_starts(J, b, s);
+    return e != hipSuccess ? e : launch_scatter(J, b, s);
 }
 
 }  // namespace bsort

@@ -41,7 +41,9 @@ __device__ __forceinline__ int gadd(int32_t* p, int v) {
     return __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
+// write_ko: 0 when the bucketize pass of the same call has already written
+// key_off (the same values), which its scatter may be reading meanwhile
+__global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J, int write_ko) {
     __shared__ int64_t kos[kTileWavesPerBlock][kMaxLen + 1];
     __shared__ int blk_tiles[kNumD];
     __shared__ int64_t blk_tile_base[kNumD];
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J) {
             run += __shfl(incl, kWave - 1, kWave);
             if (L >= ml1) continue;
             kos[wv][L] = ko;
-            J->key_off[(int64_t)r * ml1 + L] = ko;
+            if (write_ko) J->key_off[(int64_t)r * ml1 + L] = ko;
             if (L == 0 || nb < 2) continue;  // 0 or 1 word: already in order
             if (st[L] < 0 || (int64_t)st[L] + nb > b - a ||
                 ko + (int64_t)lanes_for_len(L) * nb > (int64_t)wmax * b) {
@@ -406,13 +408,14 @@ hipError_t launch_merge_one_bucket(const Job* J, const MergeItem& item0, int npa
     return hipGetLastError();
 }
 
-hipError_t launch_sort_prep(const Job* J, const Bounds& b, hipStream_t s) {
+hipError_t launch_sort_prep(const Job* J, const Bounds& b, bool after_bucketize, hipStream_t s) {
     if (!b.fused_pack) {
         hipError_t e = launch_chunk_plan(J, b, false, s);   // k_pack's chunk map
         if (e != hipSuccess) return e;
     }
     k_sort_init<<<grid_for2((int64_t)b.phase_bound + kNumD + 1, 256, 1024), 256, 0, s>>>(J);
-    k_tile_plan<<<grid_for2(b.R, kTileWavesPerBlock, 0x7fffffff), 256, 0, s>>>(J);
+    k_tile_plan<<<grid_for2(b.R, kTileWavesPerBlock, 0x7fffffff), 256, 0, s>>>(
+        J, after_bucketize && b.fused_pack ? 0 : 1);
     // keys already written by the scatter when it packs (batched form)
     return b.fused_pack ? hipGetLastError() : launch_pack(J, b, s);
 }
