@@ -47,16 +47,16 @@ PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 128 B/clk/CU LDS bandwidth: 78.6
 SORT_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TOK_SOURCES = ("paper_1407_6603_amd/csrc/k_tokenize.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TRAFFIC = {
-    "k_bucket_lds<2, 1024, 16384>": {"read": 66702144, "write": 22090472,
-                                     "files": SORT_SOURCES, "sources": "01157a2813442cec"},
-    "k_bucket_lds<3, 1024, 8192>": {"read": 38605206, "write": 12720696,
-                                    "files": SORT_SOURCES, "sources": "01157a2813442cec"},
-    "k_tok_count": {"read": 189662544, "write": 740160,
-                    "files": TOK_SOURCES, "sources": "e923714993a4c7e1"},
+    "k_bucket_lds<2, 1024, 16384>": {"read": 66702384, "write": 22090288,
+                                     "files": SORT_SOURCES, "sources": "e8a357db5266dc54"},
+    "k_bucket_lds<3, 1024, 8192>": {"read": 38602015, "write": 12720800,
+                                    "files": SORT_SOURCES, "sources": "e8a357db5266dc54"},
+    "k_tok_count": {"read": 189666685, "write": 746000,
+                    "files": TOK_SOURCES, "sources": "68fd582c5aaea8f0"},
     "k_tok_scan": {"read": 110204, "write": 183712,
-                   "files": TOK_SOURCES, "sources": "e923714993a4c7e1"},
-    "k_tok_write": {"read": 191129687, "write": 403946576,
-                    "files": TOK_SOURCES, "sources": "e923714993a4c7e1"},
+                   "files": TOK_SOURCES, "sources": "68fd582c5aaea8f0"},
+    "k_tok_write": {"read": 191130437, "write": 403942352,
+                    "files": TOK_SOURCES, "sources": "68fd582c5aaea8f0"},
 }
 
 
