@@ -168,9 +168,12 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
  * (phases through HBM).  bsort_stage_count(max_len) is their number and
  * bsort_stage_name(max_len, i) the name of stage i (NULL if out of range).
  *
- * bucketize and pack run in order on the caller's stream, then the tile
- * stages and merge_split, in that order (merge_split merges the tiles the
- * tile stages sort).  The in-LDS stages touch sub-arrays of their own; they
+ * bucketize runs on the caller's stream.  pack needs only bucketize's counts
+ * and starts, so it runs beside bucketize's final scatter on a library stream
+ * and is joined back before the sort stages (with BSORT_FLAG_SERIAL_STAGES,
+ * or in bsort_sort_buckets, it follows on the caller's stream).  Then the
+ * tile stages and merge_split run on the caller's stream, in that order
+ * (merge_split merges the tiles the tile stages sort).  The in-LDS stages touch sub-arrays of their own; they
  * are queued after the tile stages and run concurrently with them and with
  * merge_split on three library streams (default priority), joined back into
  * the caller's stream before the call's work ends.  With
