@@ -73,7 +73,25 @@ class Workspace:
         if nbytes:
             self.ensure(nbytes)
 
+    @classmethod
+    def wrap(cls, region: "torch.Tensor") -> "Workspace":
+        """A workspace over an existing 256-byte aligned uint8 device region
+        (no allocation; ensure() raises if a call needs more)."""
+        if region.dtype != torch.uint8 or not region.is_cuda or not region.is_contiguous():
+            raise ValueError("a workspace region is a contiguous uint8 device tensor")
+        if region.data_ptr() % 256:
+            raise ValueError("a workspace region must be 256-byte aligned")
+        ws = cls(device=region.device)
+        ws.tensor = region
+        ws.nbytes = region.numel()
+        ws.fixed = True
+        return ws
+
+    fixed = False
+
     def ensure(self, nbytes: int):
+        if nbytes > self.nbytes and self.fixed:
+            raise ValueError(f"workspace region of {self.nbytes} bytes, {nbytes} needed")
         if nbytes > self.nbytes:
             self.tensor = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
             self.nbytes = nbytes
@@ -82,7 +100,7 @@ class Workspace:
     @property
     def ptr(self) -> int:
         p = self.tensor.data_ptr()
-        return (p + 255) & ~255
+        return p if self.fixed else (p + 255) & ~255
 
 
 def _ws_for(ws: Optional[Workspace], nbytes: int, device) -> Workspace:

@@ -100,6 +100,148 @@ def test_deterministic_replay():
         assert np.array_equal(x.perm, y.perm)
 
 
+def test_refused_request_in_the_middle_splits_the_batch():
+    """Requests 0 and 2 are admitted and 1 (between them in the staging
+    arrays) is refused: a batch is one run of the staging arrays, so 0 and 2
+    go in separate batches and each gets its own words."""
+    staging, reqs, lists = make_requests([100, 5000, 120, 90], [0.0, 0.0, 0.0, 0.0])
+    res, _, ex = run_virtual(staging, reqs, pool=64 * 1000)
+    assert [r.refused for r in res] == [False, True, False, False]
+    for h in ex.log:
+        assert 1 not in h["rids"]
+        assert not (0 in h["rids"] and 2 in h["rids"])
+    for k in (0, 2, 3):
+        assert np.array_equal(res[k].perm, oracle_sort(lists[k].bytes, lists[k].offsets))
+
+
+def test_arrival_order_unlike_staging_order_splits_batches():
+    staging, reqs, lists = make_requests([80, 90, 100, 110], [0.003, 0.001, 0.002, 0.0])
+    res, _, ex = run_virtual(staging, reqs, pool=1 << 30, slots=1, cost=lambda w: 0.01)
+    for h in ex.log:
+        a, b = h["words"]
+        assert b - a == sum(reqs[r].n for r in h["rids"])
+    for r, w in zip(res, lists):
+        assert np.array_equal(r.perm, oracle_sort(w.bytes, w.offsets))
+
+
+def test_ring_arena_blocks_never_overlap():
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        cap = int(rng.integers(1, 64)) * 4096
+        ar = serve.RingArena(cap)
+        live = {}
+        for step in range(400):
+            if live and (rng.random() < 0.45 or len(live) > 12):
+                off = list(live)[int(rng.integers(len(live)))]
+                ar.free(off)
+                del live[off]
+            else:
+                size = int(rng.integers(1, cap // 3 + 2))
+                off = ar.alloc(size)
+                if off is None:
+                    continue
+                sz = serve._up(size)
+                assert 0 <= off and off + sz <= ar.capacity and off % serve.ALIGN == 0
+                for o, z in live.items():
+                    assert off + sz <= o or o + z <= off, "blocks overlap"
+                live[off] = sz
+            assert ar.used == sum(live.values())
+        for off in list(live):
+            ar.free(off)
+        assert ar.alloc(ar.capacity) == 0          # everything freed: the whole arena fits
+
+
+def test_footprints_cover_the_batch_layout():
+    """A batch's buffers fit in the span its members' footprints hold (the
+    library's workspace size is sub-additive over lists)."""
+    from paper_1407_6603_amd import _lib
+    L = _lib.load()
+    wsb = lambda n, ml, R: int(L.bsort_workspace_bytes(n, ml, R))
+    rng = np.random.default_rng(9)
+    for ml in (1, 12, 32, 64):
+        for trial in range(60):
+            R = int(rng.integers(1, 40))
+            ns = np.floor(10 ** rng.uniform(0, 6.5, R)).astype(np.int64)
+            ns[rng.random(R) < 0.1] = 0
+            nb = [int(n * rng.uniform(1, 8)) for n in ns]
+            fp = sum(serve.request_footprint(int(n), b, ml, wsb) for n, b in zip(ns, nb))
+            lay = serve.batch_layout(sum(nb), int(ns.sum()), R, wsb(int(ns.sum()), ml, R))
+            assert lay["size"] <= fp
+
+
+def test_cancel_queued_request_frees_its_place():
+    """Pool for two requests: 0 and 1 run, 2 waits for the pool and is
+    cancelled; 3 then takes its place and every other result is exact."""
+    sizes = [400] * 5
+    staging, reqs, lists = make_requests(sizes, [0.0] * 5)
+    fp = 64 * 400 + max(r.n_bytes for r in reqs)
+    pool = serve._up(fp) * 2 + 512
+    clock = serve.VirtualClock()
+    ex = serve.HostExecutor(staging, oracle_sort, clock, slots=2, cost=lambda w: 0.01)
+    srv = serve.Server(ex, pool_bytes=pool, clock=clock)
+    res = srv.run(reqs, cancels=[(0.001, 2), (0.001, 0), (0.5, 4)])
+    assert res[2].cancelled and res[2].launched is None and res[2].perm is None
+    assert not res[0].cancelled                  # launched at 0: the cancel came too late
+    assert not res[4].cancelled                  # done before its cancel
+    assert all(2 not in h["rids"] for h in ex.log)
+    assert res[3].launched == pytest.approx(0.01)   # admitted when 0 and 1 finished
+    for k in (0, 1, 3, 4):
+        assert np.array_equal(res[k].perm, oracle_sort(lists[k].bytes, lists[k].offsets))
+    st = serve.latency_stats(res)
+    assert st["cancelled"] == 1 and st["requests"] == 4
+    assert srv.pool_used == 0
+
+
+def test_cancel_before_arrival_and_of_admitted_request():
+    staging, reqs, lists = make_requests([300, 300, 300, 300], [0.0, 0.0, 0.0, 0.02])
+    clock = serve.VirtualClock()
+    ex = serve.HostExecutor(staging, oracle_sort, clock, slots=1, cost=lambda w: 0.01)
+    srv = serve.Server(ex, pool_bytes=1 << 30, clock=clock, max_batch_words=300)
+    # 1 and 2 are admitted at 0 but wait for the one slot; 3 is cancelled before it arrives
+    res = srv.run(reqs, cancels=[(0.005, 1), (0.01, 3)])
+    assert [r.cancelled for r in res] == [False, True, False, True]
+    assert res[2].launched == pytest.approx(0.01)
+    for h in ex.log:
+        assert 1 not in h["rids"] and 3 not in h["rids"]
+    for k in (0, 2):
+        assert np.array_equal(res[k].perm, oracle_sort(lists[k].bytes, lists[k].offsets))
+    assert srv.pool_used == 0
+
+
+@pytest.mark.gpu
+def test_gpu_server_small_pool_refusal_and_cancel():
+    """A pool for a few requests at a time: requests queue for memory, one
+    too large for the pool is refused in the middle of the staging arrays,
+    one queued request is cancelled; every other result equals the oracle's
+    and the same list sorted alone."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1407_6603_amd as bs
+    rng = np.random.default_rng(77)
+    n = 24
+    sizes = np.floor(1000 * (30 ** rng.random(n))).astype(int)
+    sizes[9] = 200_000                           # refused: larger than the pool
+    arrivals = np.sort(rng.uniform(0, 0.004, n))
+    staging, reqs, lists = make_requests(sizes, arrivals, seed=8, lmax=12)
+    fps = [serve.request_footprint(r.n, r.n_bytes, 12, bs.workspace_bytes) for r in reqs]
+    pool = serve._up(max(fp for i, fp in enumerate(fps) if i != 9)) * 3
+    assert fps[9] > pool
+    ex = serve.GpuExecutor(staging, arena_bytes=pool, streams=2)
+    srv = serve.Server(ex, clock=serve.WallClock())
+    res = srv.run(reqs, cancels=[(float(arrivals[15]), 15)])
+    assert res[9].refused
+    assert srv.pool_high <= pool
+    ws = bs.Workspace()
+    for k, (r, w) in enumerate(zip(res, lists)):
+        if k == 9 or r.cancelled:
+            continue
+        expect = oracle.definition_sort(w.bytes, w.offsets)
+        assert np.array_equal(r.perm, expect), f"request {k}"
+        b, o = bs.to_device(w.bytes, w.offsets)
+        assert np.array_equal(bs.sort(b, o, 12, ws=ws).cpu().numpy(), expect)
+
+
 @pytest.mark.gpu
 def test_gpu_server_results_same_alone_and_in_the_mix():
     import torch
@@ -111,8 +253,8 @@ def test_gpu_server_results_same_alone_and_in_the_mix():
     sizes = np.floor(1000 * (100 ** rng.random(n))).astype(int)      # 1e3 .. 1e5 words
     arrivals = np.cumsum(rng.exponential(1 / 2000.0, n))
     staging, reqs, lists = make_requests(sizes, arrivals, seed=7, lmax=12)
-    ex = serve.GpuExecutor(staging, streams=3)
-    srv = serve.Server(ex, pool_bytes=1 << 30)
+    ex = serve.GpuExecutor(staging, arena_bytes=1 << 30, streams=3)
+    srv = serve.Server(ex)
     res = srv.run(reqs)
     ws = bs.Workspace()
     for r, w in zip(res, lists):
