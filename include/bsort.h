@@ -25,12 +25,22 @@
  *     or keeps it beyond the call's stream work.  Arrays named "host" are
  *     host memory read during the call only.
  *   - Calls are asynchronous on the given stream (a hipStream_t passed as
- *     void*; NULL is the null stream) unless stated otherwise.  Outputs are
- *     valid once the stream reaches the call's work.
+ *     void*; NULL is the null stream) unless stated otherwise: the sorting
+ *     calls never wait for the device or read anything back (every launch
+ *     size is fixed on the host; the merge-split work of sub-arrays larger
+ *     than LDS is found on the device by one launch).  Outputs are valid
+ *     once the stream reaches the call's work.
  *   - No entry point allocates device memory except bsort_plan_create.
  *     Scratch space is a caller-allocated workspace of at least
  *     bsort_workspace_bytes(...) bytes, 256-byte aligned.  Calls that run
  *     concurrently must use distinct workspaces.
+ *   - Objects the library owns: plans (bsort_plan_create .. destroy), and,
+ *     per device, up to four pools of three HIP streams (default priority)
+ *     with their fork/join events.  A batch sort that fans its in-LDS stages
+ *     out (the default; see bsort_sort_batch_staged) takes the pool of its
+ *     caller's stream, creating it on first use, and keeps it until the
+ *     process ends.  BSORT_FLAG_SERIAL_STAGES runs everything on the
+ *     caller's stream and creates nothing.
  *   - Host-side argument checks return a status synchronously and launch
  *     nothing when they fail.  Faults found on the device (a word longer than
  *     max_len, offsets that decrease or point past n_bytes, request bounds
@@ -109,6 +119,11 @@ typedef struct {
  * slower, but each stage then has the GPU to itself (per-stage timing) and
  * no work runs outside the caller's stream. */
 #define BSORT_FLAG_SERIAL_STAGES 4
+/* Testing only: every wait of the merge-split launch gives up at once, as a
+ * bounded wait does when the work it waits for never completes: the launch
+ * ends, bsort_get_device_status reports BSORT_E_INVALID ("a wait of the
+ * merge-split launch gave up") and perm is unspecified. */
+#define BSORT_FLAG_STALL_TEST 8
 
 /* Workspace bytes for up to total_words words in up to n_requests lists with
  * words of at most max_len bytes.  Returns 0 for invalid arguments. */
@@ -165,18 +180,21 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
  * D = 2 .. min(9, ceil(max_len/4)+1) (sub-arrays sorted whole in LDS; C =
  * 1024, 2048, 4096, 8192 where D*4*C <= 144 KiB, and a largest class of
  * 16384, 12288, 9216 or 7168 words for D = 2, 3, 4, 5), and "merge_split"
- * (phases through HBM).  bsort_stage_count(max_len) is their number and
- * bsort_stage_name(max_len, i) the name of stage i (NULL if out of range).
+ * (sub-arrays larger than LDS: their chunks sorted in LDS, then one launch
+ * that runs every merge-split phase of every such sub-array).
+ * bsort_stage_count(max_len) is their number and bsort_stage_name(max_len, i)
+ * the name of stage i (NULL if out of range).
  *
  * bucketize runs on the caller's stream.  pack needs only bucketize's counts
  * and starts, so it runs beside bucketize's final scatter on a library stream
  * and is joined back before the sort stages (with BSORT_FLAG_SERIAL_STAGES,
  * or in bsort_sort_buckets, it follows on the caller's stream).  Then the
  * tile stages and merge_split run on the caller's stream, in that order
- * (merge_split merges the tiles the tile stages sort).  The in-LDS stages touch sub-arrays of their own; they
- * are queued after the tile stages and run concurrently with them and with
- * merge_split on three library streams (default priority), joined back into
- * the caller's stream before the call's work ends.  With
+ * (merge_split merges the tiles the tile stages sort).  The in-LDS stages
+ * touch sub-arrays of their own; they are queued after the tile stages and
+ * run concurrently with them and with merge_split on three library streams
+ * (default priority), joined back into the caller's stream before the call's
+ * work ends.  With
  * BSORT_FLAG_SERIAL_STAGES every stage runs on the caller's stream in the
  * order tiles, in-LDS classes, merge_split.
  *

@@ -20,6 +20,7 @@ STATUS = {0: "BSORT_OK", 1: "BSORT_E_INVALID", 2: "BSORT_E_TOO_LONG", 3: "BSORT_
 FLAG_PER_BUCKET_LAUNCH = 1
 FLAG_TILES_ONLY = 2
 FLAG_SERIAL_STAGES = 4
+FLAG_STALL_TEST = 8
 KEY_BYTES, KEY_LENGTH, KEY_LENGTH_BYTES = 0, 1, 2
 LAYOUT_PACKED, LAYOUT_TEXT = 0, 1
 

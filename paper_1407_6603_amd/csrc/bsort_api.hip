@@ -39,9 +39,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // size a caller asks for and the layout a call uses always agree.
 struct Layout {
     size_t status, job, chunk_begin, chunk_list, chunk_hist, key_off, keys, tiles[kNumD], tile_count,
-        mlist[2], mcount, counts, starts, order, jobs, lbuckets, lb_count,
-        hchunks[kLdsMaxD + 1], hc_count, pmax;
-    int64_t chunk_cap, tile_cap, merge_cap, lb_cap;
+        msub, msorted, mcounts, tile_ph, pcnt, pfill, active, pe, po, ps, mhead, counts, starts,
+        order, jobs, lbuckets, lb_count, hchunks[kLdsMaxD + 1], hc_count, pmax;
+    int64_t chunk_cap, tile_cap, msub_cap, lb_cap;
     int32_t phase_cap, ml1, dmax, wmax;
     size_t bytes;
 };
@@ -55,7 +55,8 @@ bool make_layout(int64_t total, int32_t R, int32_t max_len, Layout& L) {
     const int64_t tiles_total = (total + kMinTile - 1) / kMinTile;
     L.chunk_cap = (total + kChunk - 1) / kChunk + R;
     L.tile_cap = tiles_total + 4 * (int64_t)R;
-    L.merge_cap = (tiles_total + (int64_t)R * L.ml1) / 2 + 1;
+    // a sub-array merged through HBM has two tiles of at least kMinTile words
+    L.msub_cap = tiles_total / 2 + 1;
     L.phase_cap = (int32_t)std::min<int64_t>(tiles_total + 2, kMaxPhaseCap);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -80,9 +81,17 @@ bool make_layout(int64_t total, int32_t R, int32_t max_len, Layout& L) {
         L.hchunks[D] = take(sizeof(LBucket) * (size_t)L.tile_cap);
     L.hc_count = take(sizeof(int32_t) * (kLdsMaxD + 1));
     L.pmax = take(sizeof(int32_t));
-    L.mlist[0] = take(sizeof(MergeItem) * (size_t)L.merge_cap);
-    L.mlist[1] = take(sizeof(MergeItem) * (size_t)L.merge_cap);
-    L.mcount = take(sizeof(int32_t) * ((size_t)L.phase_cap + 1));
+    L.msub = take(sizeof(MSub) * (size_t)L.msub_cap);
+    L.msorted = take(sizeof(MSub) * (size_t)L.msub_cap);
+    L.mcounts = take(2 * sizeof(int32_t));
+    L.tile_ph = take(sizeof(int32_t) * (size_t)L.tile_cap);
+    L.pcnt = take(sizeof(int32_t) * ((size_t)L.phase_cap + 2));
+    L.pfill = take(sizeof(int32_t) * ((size_t)L.phase_cap + 2));
+    L.active = take(sizeof(int32_t) * ((size_t)L.phase_cap + 2));
+    L.pe = take(sizeof(int64_t) * ((size_t)L.msub_cap + 1));
+    L.po = take(sizeof(int64_t) * ((size_t)L.msub_cap + 1));
+    L.ps = take(sizeof(int64_t) * ((size_t)L.phase_cap + 1));
+    L.mhead = take(4 * sizeof(int64_t));
     L.counts = take(sizeof(int32_t) * (size_t)R * L.ml1);
     L.starts = take(sizeof(int32_t) * (size_t)R * (L.ml1 + 1));
     L.order = take(sizeof(int32_t) * (size_t)total);
@@ -103,8 +112,8 @@ bsort_status check_tuning(const bsort_tuning* t) {
     if (t->merge_threads != 0 &&
         (t->merge_threads < 64 || t->merge_threads > 1024 || t->merge_threads % 64))
         return fail(BSORT_E_INVALID, "merge_threads must be 0 or a multiple of 64 in [64, 1024]");
-    if (t->flags &
-        ~(BSORT_FLAG_PER_BUCKET_LAUNCH | BSORT_FLAG_TILES_ONLY | BSORT_FLAG_SERIAL_STAGES))
+    if (t->flags & ~(BSORT_FLAG_PER_BUCKET_LAUNCH | BSORT_FLAG_TILES_ONLY |
+                     BSORT_FLAG_SERIAL_STAGES | BSORT_FLAG_STALL_TEST))
         return fail(BSORT_E_INVALID, "unknown flag");
     return BSORT_OK;
 }
@@ -159,7 +168,7 @@ Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
     // twice the inputs when that fits: merged output staged in LDS, written coalesced
     b.merge_lds = std::max(1024, std::min(budget, 2 * need));
     b.lb_cap = L.lb_cap;
-    b.phase_bound = (int32_t)std::min<int64_t>(pb, L.phase_cap);
+    b.hbm_merge = pb > 1;
     b.pair_lds = pair_merge_lds(L.dmax);
     return b;
 }
@@ -195,12 +204,22 @@ Job base_job(const Layout& L, char* ws, const Bounds& b) {
     j.lb_take = j.lb_back + kNumD * kLdsClasses;
     j.lb_cap = L.lb_cap;
     j.tile_count = (int32_t*)(ws + L.tile_count);
-    j.mlist[0] = (MergeItem*)(ws + L.mlist[0]);
-    j.mlist[1] = (MergeItem*)(ws + L.mlist[1]);
-    j.merge_cap = L.merge_cap;
-    j.mcount = (int32_t*)(ws + L.mcount);
+    j.msub = (MSub*)(ws + L.msub);
+    j.msorted = (MSub*)(ws + L.msorted);
+    j.msub_cap = L.msub_cap;
+    j.mcounts = (int32_t*)(ws + L.mcounts);
+    j.tile_ph = (int32_t*)(ws + L.tile_ph);
+    j.mtile_cap = L.tile_cap;
+    j.pcnt = (int32_t*)(ws + L.pcnt);
+    j.pfill = (int32_t*)(ws + L.pfill);
+    j.active = (int32_t*)(ws + L.active);
+    j.pe = (int64_t*)(ws + L.pe);
+    j.po = (int64_t*)(ws + L.po);
+    j.ps = (int64_t*)(ws + L.ps);
+    j.mhead = (int64_t*)(ws + L.mhead);
     j.phase_cap = L.phase_cap;
-    j.phase_bound = b.phase_bound;
+    // a wait of the merge launch gives up after 4 s (100 MHz counter)
+    j.stall_ticks = (b.flags & BSORT_FLAG_STALL_TEST) ? -1 : 400000000;
     return j;
 }
 
@@ -342,7 +361,7 @@ bsort_status bsort_bucketize(const bsort_words* w, const bsort_buckets* b, void*
 }
 
 static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
-                               void* const* ev, const int32_t* d_pmax);
+                               void* const* ev);
 
 bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, int32_t* perm,
                                 const bsort_tuning* t, void* ws, size_t ws_bytes,
@@ -367,7 +386,7 @@ bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, in
     j.order = b->order;
     j.perm = perm;
     HIP_TRY(launch_set_job(j, jd, s));
-    HIP_TRY(enqueue_sort(jd, bd, s, false, nullptr, j.pmax));
+    HIP_TRY(enqueue_sort(jd, bd, s, false, nullptr));
     return BSORT_OK;
 }
 
@@ -485,14 +504,11 @@ constexpr int kMaxDevices = 64;
 struct FanPool {
     std::mutex mu;
     bool ready = false;             // streams and fork/join events
-    bool rb_ready = false;          // phase-count read-back event and pinned word
     hipStream_t aux[kFan - 1] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kFan - 1] = {};
     hipEvent_t prep_fork = nullptr;  // the plan beside the scatter, on aux[0]
     hipEvent_t prep_join = nullptr;
-    hipEvent_t pmax_ev = nullptr;   // the merge-split phase count has reached the host
-    int32_t* host_pmax = nullptr;   // pinned
 };
 
 static FanPool g_fan[kMaxDevices][kFanPools];
@@ -511,16 +527,8 @@ static int fan_pool_for(int dev, hipStream_t s) {
     return k;
 }
 
-static hipError_t fan_init_readback(FanPool& f) {
-    if (f.rb_ready) return hipSuccess;
-    hipError_t e = hipEventCreateWithFlags(&f.pmax_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&f.host_pmax, sizeof(int32_t), 0);
-    if (e == hipSuccess) f.rb_ready = true;
-    return e;
-}
-
 static hipError_t fan_init(FanPool& f) {
-    if (f.ready) return fan_init_readback(f);
+    if (f.ready) return hipSuccess;
     hipError_t e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&f.prep_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&f.prep_join, hipEventDisableTiming);
@@ -528,7 +536,6 @@ static hipError_t fan_init(FanPool& f) {
         e = hipStreamCreateWithFlags(&f.aux[k], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&f.join[k], hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = fan_init_readback(f);
     if (e == hipSuccess) f.ready = true;
     return e;
 }
@@ -565,12 +572,11 @@ static std::vector<StageRef> sort_stages(const Bounds& b) {
     return v;
 }
 
-static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, hipStream_t s,
-                            int phases) {
+static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, hipStream_t s) {
     switch (st.kind) {
         case kStageTiles: return launch_oets_tiles_one(J, b, st.D, s);
         case kStageLds: return launch_lds_class(J, b, st.D, st.c, s);
-        default: return launch_merges(J, b, phases, s);
+        default: return launch_merges(J, b, s);
     }
 }
 
@@ -580,13 +586,11 @@ static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, h
 // a library stream beside the scatter; otherwise everything before the sort
 // stages is on the caller's stream.
 // ev (optional): 2 events per stage in bsort_stage_name order, recorded just
-// before and after the stage on the stream that runs it.  d_pmax (optional):
-// the job's device word holding the most merge-split phases any sub-array
-// needs; outside graph capture it is read back once the plan is made (the
-// in-LDS classes already running) so exactly that many phases are launched
-// instead of the bound from the largest list.
+// before and after the stage on the stream that runs it.  Nothing is read
+// back: every launch size is fixed on the host, and the merge-split phases run
+// in one launch that finds its work on the device.
 static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
-                               void* const* ev, const int32_t* d_pmax) {
+                               void* const* ev) {
     auto rec = [&](int i, int end, hipStream_t x) -> hipError_t {
         return ev && ev[2 * i + end] ? hipEventRecord((hipEvent_t)ev[2 * i + end], x) : hipSuccess;
     };
@@ -594,20 +598,14 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     // BSORT_FLAG_SERIAL_STAGES: every stage on s and no library stream
     const bool fan = !(b.flags & BSORT_FLAG_SERIAL_STAGES);
     const bool prep_beside = fan && bucketize && b.fused_pack;
-    bool readback = false;
-    if (d_pmax && b.phase_bound > 4 && !(b.flags & kFlagTilesOnly)) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return e;
-        readback = cs == hipStreamCaptureStatusNone;
-    }
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     FanPool& f = g_fan[dev][fan ? fan_pool_for(dev, s) : 0];
     std::unique_lock<std::mutex> lock(f.mu, std::defer_lock);
-    if (fan || readback) {
+    if (fan) {
         lock.lock();
-        if ((e = fan ? fan_init(f) : fan_init_readback(f)) != hipSuccess) return e;
+        if ((e = fan_init(f)) != hipSuccess) return e;
     }
     if (bucketize) {
         if ((e = rec(0, 0, s)) != hipSuccess) return e;
@@ -630,12 +628,6 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
         if ((e = launch_sort_prep(J, b, bucketize, s)) != hipSuccess) return e;
         if ((e = rec(1, 1, s)) != hipSuccess) return e;
     }
-    if (readback) {
-        if ((e = hipMemcpyAsync(f.host_pmax, d_pmax, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                s)) != hipSuccess)
-            return e;
-        if ((e = hipEventRecord(f.pmax_ev, s)) != hipSuccess) return e;
-    }
     hipStream_t st[kFan] = {s, f.aux[0], f.aux[1], f.aux[2]};
     if (fan) {
         if ((e = hipEventRecord(f.fork, s)) != hipSuccess) return e;
@@ -649,7 +641,7 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     for (const StageRef& g : stages) {
         if (g.kind != kStageTiles) continue;
         if ((e = rec(g.index, 0, s)) != hipSuccess) return e;
-        if ((e = run_stage(g, J, b, s, -1)) != hipSuccess) return e;
+        if ((e = run_stage(g, J, b, s)) != hipSuccess) return e;
         if ((e = rec(g.index, 1, s)) != hipSuccess) return e;
     }
     int lds_seen = 0;
@@ -657,18 +649,13 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
         if (g.kind != kStageLds) continue;
         hipStream_t x = fan ? st[1 + (lds_seen++) % (kFan - 1)] : s;
         if ((e = rec(g.index, 0, x)) != hipSuccess) return e;
-        if ((e = run_stage(g, J, b, x, -1)) != hipSuccess) return e;
+        if ((e = run_stage(g, J, b, x)) != hipSuccess) return e;
         if ((e = rec(g.index, 1, x)) != hipSuccess) return e;
     }
     for (const StageRef& g : stages) {
         if (g.kind != kStageMerge) continue;
-        int phases = -1;
-        if (g.kind == kStageMerge && readback) {
-            if ((e = hipEventSynchronize(f.pmax_ev)) != hipSuccess) return e;
-            phases = *f.host_pmax;
-        }
         if ((e = rec(g.index, 0, s)) != hipSuccess) return e;
-        if ((e = run_stage(g, J, b, s, phases)) != hipSuccess) return e;
+        if ((e = run_stage(g, J, b, s)) != hipSuccess) return e;
         if ((e = rec(g.index, 1, s)) != hipSuccess) return e;
     }
     for (int k = 1; fan && k < kFan; ++k) {
@@ -703,7 +690,7 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
     Job* jd = (Job*)((char*)ws + L.job);
     Job j = batch_job(L, (char*)ws, bd, b, total, perm);
     HIP_TRY(launch_set_job(j, jd, s));
-    HIP_TRY(enqueue_sort(jd, bd, s, true, events, j.pmax));
+    HIP_TRY(enqueue_sort(jd, bd, s, true, events));
     return BSORT_OK;
 }
 
@@ -757,7 +744,7 @@ bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap
     if (e == hipSuccess) e = fan_prepare(cs);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = enqueue_sort(p->job_dev, p->bd, cs, true, nullptr, nullptr);
+        hipError_t e1 = enqueue_sort(p->job_dev, p->bd, cs, true, nullptr);
         e = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = e1;
     }
@@ -813,6 +800,7 @@ bsort_status bsort_get_device_status(void* ws, bsort_stream_t stream) {
     if (v & ST_BAD_OFFSETS) what += " offsets decrease or pass n_bytes;";
     if (v & ST_BAD_REQ) what += " request bounds inconsistent;";
     if (v & ST_OVERFLOW) what += " internal list overflow;";
+    if (v & ST_STALLED) what += " a wait of the merge-split launch gave up;";
     g_err = "device status:" + what;
     if (v & ST_TOO_LONG) return BSORT_E_TOO_LONG;
     return BSORT_E_INVALID;
@@ -929,7 +917,6 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
             m.a = 0;
             m.p = nt;
             m.s = 0;
-            m.pair_base = 0;
             const int lds = std::min(merge_lds_budget(), 2 * D * 2 * T * 4);
             for (int ph = 0; ph < nt; ++ph) {
                 const int npairs = (nt - (ph & 1)) / 2;

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "merge_sched.h"
+
 namespace bsort {
 
 // Views of pointers as global memory.  Pointers read from the job
@@ -45,11 +47,11 @@ constexpr int kChunk = kWave * kChunkRounds;   // words per bucketize chunk
 constexpr int kTileWavesPerBlock = 4;
 constexpr int kMinTile = 128;             // 64 lanes x 2 records
 constexpr int kFlagTilesOnly = 2;         // same value as BSORT_FLAG_TILES_ONLY
+// Job.flags: leave the status word as it is
 constexpr int kJobKeepStatus = 1 << 8;
 // Job.flags: the scatter by length also packs each word's key lanes and index
 // payload at its place in the sub-array (batched form; order is not written)
-constexpr int kJobFusedPack = 1 << 9;    // Job.flags: leave the status word as it is
-constexpr int kMergeGrid = 1024;          // workgroups of the persistent merge kernel
+constexpr int kJobFusedPack = 1 << 9;
 constexpr int kMaxPhaseCap = 1 << 22;
 
 // device status bits (workspace status word)
@@ -58,7 +60,7 @@ enum : uint32_t {
     ST_TOO_LONG = 2u,
     ST_BAD_REQ = 4u,
     ST_OVERFLOW = 8u,      // an internal list bound was exceeded (a library bug)
-    ST_STALLED = 16u,      // a bounded wait in the merge scheduler gave up (a library bug)
+    ST_STALLED = 16u,      // a bounded wait of the merge-split launch gave up (a library bug)
 };
 
 // In-LDS sub-arrays: one workgroup holds a whole sub-array of up to
@@ -150,16 +152,25 @@ struct LBucket {             // a sub-array (or a chunk of one) sorted entirely 
     int32_t wk;              // nonzero: write the sorted keys back (a chunk merged later)
 };
 
-struct MergeItem {           // merge-split of tiles a and a+1 of a bucket at phase s
+struct MergeItem {           // plain form: merge-split of tiles a and a+1 of a bucket
     int64_t pos0;
     int64_t key_off;
-    int64_t pair_base;       // arrival counters of this bucket's pairs start here
     int32_t n_b;
     int32_t L;
     int32_t T;               // tile size of this bucket
     int32_t a;               // lower tile
     int32_t p;               // tiles in the bucket
     int32_t s;               // phase
+};
+
+struct MSub {                // a sub-array merged through HBM (batched form)
+    int64_t pos0;            // global position of its first word
+    int64_t key_off;         // uint64 index of its lane 0
+    int64_t tile_base;       // its tiles' entries in the tile phase table
+    int32_t n_b;             // words
+    int32_t L;               // word length
+    int32_t T;               // tile size (a power of two)
+    int32_t p;               // tiles, >= 2
 };
 
 struct Job {
@@ -203,12 +214,23 @@ struct Job {
     LBucket* hchunks[kLdsMaxD + 1];   // [tile_cap[D]] each
     int32_t* hc_count;           // [kLdsMaxD + 1]
     int32_t* pmax;               // [1] most merge-split phases any sub-array needs
-    // per-phase merge-split lists (phase s reads mlist[s&1], queues into the other)
-    MergeItem* mlist[2];
-    int64_t merge_cap;
-    int32_t* mcount;             // [phase_cap + 1]
+    // merge-split through HBM in one launch (the order is described in merge_sched.h)
+    MSub* msub;                  // [msub_cap] as planned
+    MSub* msorted;               // [msub_cap] in order of decreasing tile count
+    int64_t msub_cap;
+    int32_t* mcounts;            // [0] sub-arrays, [1] tiles in msub
+    int32_t* tile_ph;            // [mtile_cap] phases done on each tile
+    int64_t mtile_cap;
+    int32_t* pcnt;               // [phase_cap + 2] sub-arrays per tile count
+    int32_t* pfill;              // [phase_cap + 2] scatter cursors
+    int32_t* active;             // [phase_cap + 2] sub-arrays with more than s tiles
+    int64_t* pe;                 // [msub_cap + 1]
+    int64_t* po;                 // [msub_cap + 1]
+    int64_t* ps;                 // [phase_cap + 1]
+    int64_t* mhead;              // [0] next item to take, [1] items in all, [2] items done
+    int64_t stall_ticks;         // bound on one wait of the merge launch, in ticks of the
+                                 // 100 MHz counter (< 0: give up at once)
     int32_t phase_cap;
-    int32_t phase_bound;         // phases the host launches at most (counters in use)
     int64_t rs_inline[2];        // req_start storage for single-list calls
     int64_t cb_inline[2];        // chunk_begin storage for the plain form's per-list jobs
 };
@@ -311,18 +333,6 @@ __device__ __forceinline__ void pack_word(BP lo, BP hi, BP p, int L, OP out, int
     }
 }
 
-// queue a merge item for phase s1
-__device__ __forceinline__ void push_item(const Job* J, int s1, const MergeItem& m) {
-    if (s1 >= J->phase_cap) {
-        set_status(J, ST_OVERFLOW);
-        return;
-    }
-    const int slot = __hip_atomic_fetch_add(gp(J->mcount) + s1, 1, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-    if (slot < J->merge_cap) J->mlist[s1 & 1][slot] = m;
-    else set_status(J, ST_OVERFLOW);
-}
-
 // ---------------------------------------------------------------- launchers
 
 struct Bounds {              // launch sizes fixed on the host (capacities)
@@ -332,7 +342,7 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
     int64_t chunk_cap;
     int64_t tile_cap;        // tile list capacity per record width
     int32_t dmax;            // widest record in use
-    int32_t phase_bound;     // merge-split phase launches
+    int32_t hbm_merge;       // some sub-array may be merged through HBM (launch the merges)
     int32_t merge_threads;   // plain form's merge workgroup size
     int32_t merge_lds;       // plain form's dynamic LDS bytes per merge workgroup
     int32_t pair_lds;        // dynamic LDS bytes of the batched pair merge
@@ -356,11 +366,11 @@ hipError_t launch_sort_prep(const Job* J, const Bounds& b, bool after_bucketize,
 hipError_t launch_oets_tiles_one(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_buckets(const Job* J, const Bounds& b, int D, hipStream_t s);
 hipError_t launch_lds_class(const Job* J, const Bounds& b, int D, int c, hipStream_t s);
-// sub-arrays merged through HBM: chunk sorts in LDS, then `phases` merge-split
-// phases (phases < 0: the host bound b.phase_bound)
-hipError_t launch_merges(const Job* J, const Bounds& b, int phases, hipStream_t s);
+// sub-arrays merged through HBM: chunk sorts in LDS, then the merge-split
+// plan and one launch for every phase of every sub-array
+hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_hbm_chunks(const Job* J, const Bounds& b, int D, hipStream_t s);
-hipError_t launch_merge_pairs(const Job* J, const Bounds& b, int phase, hipStream_t s);
+hipError_t launch_merge_sched(const Job* J, const Bounds& b, hipStream_t s);
 // dynamic LDS the batched pair merge needs for records up to dmax dwords
 int pair_merge_lds(int dmax);
 

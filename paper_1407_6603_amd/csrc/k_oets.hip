@@ -1015,7 +1015,13 @@ hipError_t launch_hbm_chunks(const Job* J, const Bounds& b, int D, hipStream_t s
     return hipGetLastError();
 }
 
-// ---- merge-split through HBM, one tile pair per workgroup
+// ---- merge-split through HBM: every phase of every sub-array in one launch
+//
+// The work items and their order are those of merge_sched.h.  k_merge_plan
+// (one workgroup) builds the order's tables from the sub-arrays the tile
+// plan listed; k_merge_sched's workgroups then take items one at a time,
+// wait until the items that last merged their two tiles are done (a phase
+// counter per tile), merge the pair in LDS and advance both tiles' counters.
 
 // records a pair merge of width D holds in LDS: two tiles of the HBM tile
 // size (chunk size for in-LDS widths, a register tile's size otherwise)
@@ -1023,12 +1029,13 @@ __host__ __device__ constexpr int pair_cap(int D) {
     return 2 * (D <= kLdsMaxD ? hbm_chunk_max(D) : kWave * kmax_for(D));
 }
 constexpr int kPairThreads = 512;
+constexpr int kPlanThreads = 1024;
 
-// Tiles m.a and m.a+1 of one sub-array (both sorted) merged in LDS and
-// written back in place, the lower tile receiving the smaller half: one
-// phase of the in-LDS merge-split over a two-tile array.
+// Tiles a and a+1 of sub-array m (both sorted) merged in LDS and written
+// back in place, the lower tile receiving the smaller half: one phase of
+// the in-LDS merge-split over a two-tile array.
 template <int D>
-__device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, uint32_t* lds,
+__device__ void merge_pair_lds(const Job* __restrict__ J, const MSub& m, int a, uint32_t* lds,
                                int* sflag, int* win, int tid) {
     constexpr int CAP2 = pair_cap(D);
     static_assert(CAP2 * 4 * D <= kLdsBytes - 4 * (kMergeWinWords + 1), "pair merge LDS");
@@ -1036,8 +1043,8 @@ __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, ui
     constexpr int Dk = D - 1, W = (Dk + 1) / 2;
     const int T = m.T;                                 // power of two, 2T <= CAP2
     const int logT = 31 - __builtin_clz(T);
-    const int64_t lo = (int64_t)m.a * T;
-    const int rest = m.n_b - (m.a + 1) * T;
+    const int64_t lo = (int64_t)a * T;
+    const int rest = m.n_b - (a + 1) * T;
     const int nb = rest < T ? rest : T;
     const int tot = T + nb;
     const int64_t ks = m.n_b;
@@ -1058,68 +1065,227 @@ __device__ void merge_pair_lds(const Job* __restrict__ J, const MergeItem& m, ui
     if (*sflag == 0) return;                           // uniform
 #pragma unroll 4
     for (int i = tid; i < tot; i += kPairThreads) {
-        const int a = lsw(i);
+        const int q = lsw(i);
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             const uint64_t v = keys[w * ks + i];
-            lds[(2 * w) * CAP2 + a] = (uint32_t)(v >> 32);
-            if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP2 + a] = (uint32_t)v;
+            lds[(2 * w) * CAP2 + q] = (uint32_t)(v >> 32);
+            if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP2 + q] = (uint32_t)v;
         }
-        lds[Dk * CAP2 + a] = (uint32_t)perm[i];
+        lds[Dk * CAP2 + q] = (uint32_t)perm[i];
     }
     __syncthreads();
     lds_merge_phase<D, kPairThreads, CAP2, true>(lds, tot, T, logT, 2, 0, tid, win);
     for (int i = tid; i < tot; i += kPairThreads) {
-        const int a = lsw(i);
-        perm[i] = (int32_t)lds[Dk * CAP2 + a];
+        const int q = lsw(i);
+        perm[i] = (int32_t)lds[Dk * CAP2 + q];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            const uint64_t hi = lds[(2 * w) * CAP2 + a];
-            const uint64_t lo32 = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP2 + a] : 0u;
+            const uint64_t hi = lds[(2 * w) * CAP2 + q];
+            const uint64_t lo32 = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP2 + q] : 0u;
             keys[w * ks + i] = (hi << 32) | lo32;
         }
     }
 }
 
 template <int D>
-__device__ __forceinline__ void merge_pair_d(const Job* J, const MergeItem& m, uint32_t* lds,
+__device__ __forceinline__ void merge_pair_d(const Job* J, const MSub& m, int a, uint32_t* lds,
                                              int* sflag, int* win, int tid, int d) {
     if constexpr (D <= kMaxD) {
-        if (d == D) merge_pair_lds<D>(J, m, lds, sflag, win, tid);
-        else merge_pair_d<D + 1>(J, m, lds, sflag, win, tid, d);
+        if (d == D) merge_pair_lds<D>(J, m, a, lds, sflag, win, tid);
+        else merge_pair_d<D + 1>(J, m, a, lds, sflag, win, tid, d);
     }
 }
 
-// phase s: every queued tile pair of every sub-array merged through HBM; each
-// pair queues its successors of phase s+1
-__global__ __launch_bounds__(kPairThreads) void k_merge_pairs(const Job* __restrict__ J, int s) {
+// Exclusive running sum over n values with the whole workgroup: value i is
+// get(i); put(i, sum of values before i).  Each thread takes a contiguous run
+// of values.  Returns the total.  sh holds kPlanThreads/64 + 1 entries.
+template <class Get, class Put>
+__device__ int64_t block_scan(int64_t n, Get get, Put put, int64_t* sh) {
+    constexpr int NW = kPlanThreads / kWave;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t per = (n + kPlanThreads - 1) / kPlanThreads;
+    const int64_t a = (int64_t)tid * per < n ? (int64_t)tid * per : n;
+    const int64_t b = a + per < n ? a + per : n;
+    int64_t sum = 0;
+    for (int64_t i = a; i < b; ++i) sum += get(i);
+    const int64_t incl = wave_incl_scan(sum, lane);
+    if (lane == kWave - 1) sh[wv] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int w = 0; w < NW; ++w) {
+            const int64_t t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[NW] = run;
+    }
+    __syncthreads();
+    int64_t run = sh[wv] + incl - sum;
+    for (int64_t i = a; i < b; ++i) {
+        const int64_t v = get(i);
+        put(i, run);
+        run += v;
+    }
+    const int64_t total = sh[NW];
+    __syncthreads();                                   // sh is reused by the next scan
+    return total;
+}
+
+// The order's tables (merge_sched.h) from the sub-arrays the tile plan
+// listed; one workgroup.  Also clears the tile phase counters and the item
+// counter.
+__global__ __launch_bounds__(kPlanThreads) void k_merge_plan(const Job* __restrict__ J) {
+    __shared__ int64_t sh[kPlanThreads / kWave + 1];
+    const int tid = threadIdx.x;
+    int64_t H = J->mcounts[0];
+    H = H < J->msub_cap ? H : J->msub_cap;
+    const int P = J->pmax[0] < J->phase_cap ? J->pmax[0] : J->phase_cap;
+    int64_t ntiles = J->mcounts[1];
+    ntiles = ntiles < J->mtile_cap ? ntiles : J->mtile_cap;
+    const gptr<int32_t> cnt = gp(J->pcnt), fill = gp(J->pfill), act = gp(J->active);
+    const gptr<int64_t> pe = gp(J->pe), po = gp(J->po), ps = gp(J->ps);
+    const MSub* msub = J->msub;
+    MSub* sorted = J->msorted;
+    if (H == 0 || P < 2) {
+        if (tid == 0) J->mhead[1] = 0;
+        return;
+    }
+    for (int64_t i = tid; i < ntiles; i += kPlanThreads) J->tile_ph[i] = 0;
+    for (int i = tid; i <= P + 1; i += kPlanThreads) {
+        cnt[i] = 0;
+        fill[i] = 0;
+    }
+    __syncthreads();
+    // an entry's tile count, or 0 (no work) for one that does not fit the tables
+    auto tiles_of = [&](const MSub& m) -> int {
+        return m.p >= 2 && m.p <= P && m.tile_base >= 0 && m.tile_base + m.p <= ntiles ? m.p : 0;
+    };
+    for (int64_t h = tid; h < H; h += kPlanThreads) atomicAdd((int32_t*)&cnt[tiles_of(msub[h])], 1);
+    __syncthreads();
+    // active[s]: sub-arrays of more than s tiles (a running sum from the top)
+    block_scan(P + 1, [&](int64_t j) -> int64_t { return cnt[P - j]; },
+               [&](int64_t j, int64_t v) { act[P - j] = (int32_t)v; }, sh);
+    // sub-arrays in order of decreasing tile count: those with more tiles first
+    for (int64_t h = tid; h < H; h += kPlanThreads) {
+        MSub m = msub[h];
+        m.p = tiles_of(m);
+        const int64_t at = act[m.p] + atomicAdd((int32_t*)&fill[m.p], 1);
+        sorted[at] = m;
+    }
+    __syncthreads();
+    const int64_t te = block_scan(H, [&](int64_t i) -> int64_t { return sorted[i].p / 2; },
+                                  [&](int64_t i, int64_t v) { pe[i] = v; }, sh);
+    const int64_t to = block_scan(H, [&](int64_t i) -> int64_t { return (sorted[i].p - 1) / 2; },
+                                  [&](int64_t i, int64_t v) { po[i] = v; }, sh);
+    if (tid == 0) {
+        pe[H] = te;
+        po[H] = to;
+    }
+    __syncthreads();
+    const int64_t items = block_scan(
+        P, [&](int64_t s) -> int64_t { return (s & 1) ? po[act[s]] : pe[act[s]]; },
+        [&](int64_t s, int64_t v) { ps[s] = v; }, sh);
+    if (tid == 0) {
+        ps[P] = items;
+        J->mhead[1] = items;
+    }
+}
+
+// Waits until tile counter f reaches need.  The counter is polled with
+// relaxed loads (no cache invalidation per poll: with an acquiring load every
+// poll would invalidate the XCD's L2 under the workgroups that are merging);
+// one acquire fence follows the successful poll.  Bounded: gives up (and sets
+// ST_STALLED, which every other wait and every workgroup's next item then
+// sees) after J->stall_ticks of the 100 MHz real-time counter, or at once when
+// stall_ticks < 0 (a test setting).
+__device__ bool wait_tile(const Job* J, gptr<int32_t> f, int need) {
+    if (need <= 0) return true;
+    if (J->stall_ticks < 0) {
+        set_status(J, ST_STALLED);
+        return false;
+    }
+    const uint64_t t0 = wall_clock64();
+    // also bounded by the number of polls (each at least 1,024 clocks apart)
+    const int64_t max_polls = J->stall_ticks / 8 + 1;
+    for (int64_t poll = 0;; ++poll) {
+        if (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
+        if (__hip_atomic_load(gp(J->status), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+            ST_STALLED)
+            return false;
+        if (wall_clock64() - t0 > (uint64_t)J->stall_ticks || poll >= max_polls) {
+            set_status(J, ST_STALLED);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(16);
+    }
+}
+
+// Every merge-split item of every sub-array merged through HBM.  Workgroups
+// take items in the order of merge_sched.h until none is left.
+__global__ __launch_bounds__(kPairThreads) void k_merge_sched(const Job* __restrict__ J) {
     extern __shared__ uint32_t lds[];
     __shared__ int sflag;
     __shared__ int mwin[kMergeWinWords];
-    if (s >= J->phase_cap) return;
-    int cnt = J->mcount[s];
-    if (cnt > J->merge_cap) cnt = (int)J->merge_cap;
-    const MergeItem* items = J->mlist[s & 1];
+    __shared__ int item[4];                            // phase, sub-array, lower tile, go
     const int tid = threadIdx.x;
-    for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
-        const MergeItem m = items[it];
-        merge_pair_d<2>(J, m, lds, &sflag, mwin, tid, dwords_for_len(m.L));
-        if (tid == 0 && s + 1 < m.p) {
-            // successors: pair (a+1, a+2); after an odd phase also (0, 1)
-            if (m.a + 2 < m.p) {
-                MergeItem n = m;
-                n.a = m.a + 1;
-                n.s = s + 1;
-                push_item(J, s + 1, n);
+    const int64_t N = J->mhead[1];
+    if (N <= 0) return;                                // uniform
+    const int P = J->pmax[0] < J->phase_cap ? J->pmax[0] : J->phase_cap;
+    const gptr<int32_t> tph = gp(J->tile_ph);
+    // a workgroup also stops taking items after 4 stall bounds in all, and
+    // takes at most N + 1 (the last one ends it)
+    const uint64_t t_start = wall_clock64();
+    for (int64_t taken = 0; taken <= N; ++taken) {
+        if (tid == 0) {
+            int go = 0;
+            const bool stalled =
+                (__hip_atomic_load(gp(J->status), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                 ST_STALLED) != 0;
+            if (!stalled && J->stall_ticks >= 0 &&
+                wall_clock64() - t_start > 4 * (uint64_t)J->stall_ticks) {
+                set_status(J, ST_STALLED);
+            } else if (!stalled) {
+                const int64_t q = __hip_atomic_fetch_add(gp(J->mhead), (int64_t)1,
+                                                         __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                if (q < N) {
+                    const MschedItem it = msched_decode(q, gp(J->ps), P, gp(J->active),
+                                                        gp(J->pe), gp(J->po));
+                    const int p = J->msorted[it.i].p;
+                    const int64_t tb = J->msorted[it.i].tile_base;
+                    go = wait_tile(J, tph + tb + it.t, (int)msched_prev(it.s, it.t, p) + 1) &&
+                         wait_tile(J, tph + tb + it.t + 1,
+                                   (int)msched_prev(it.s, it.t + 1, p) + 1);
+                    item[0] = it.s;
+                    item[1] = it.i;
+                    item[2] = it.t;
+                }
             }
-            if ((s & 1) && m.a == 1) {
-                MergeItem n = m;
-                n.a = 0;
-                n.s = s + 1;
-                push_item(J, s + 1, n);
-            }
+            item[3] = go;
         }
-        __syncthreads();                               // LDS and sflag reused by the next item
+        __syncthreads();
+        if (!item[3]) break;                           // uniform: no item left, or a stall
+        const int s = item[0], t = item[2];
+        const MSub m = J->msorted[item[1]];
+        merge_pair_d<2>(J, m, t, lds, &sflag, mwin, tid, dwords_for_len(m.L));
+        // this wave's stores have reached the cache before the barrier; the
+        // release below writes the cache back before the counters move
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(tph + m.tile_base + t, s + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(tph + m.tile_base + t + 1, s + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gp(J->mhead) + 2, (int64_t)1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -1128,7 +1294,7 @@ int pair_merge_lds(int dmax) {
     for (int D = 2; D <= dmax && D <= kMaxD; ++D) need = std::max(need, pair_cap(D) * 4 * D);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_merge_pairs,
+        (void)hipFuncSetAttribute((const void*)k_merge_sched,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   kLdsBytes - 4 * (kMergeWinWords + 1));
         attr = true;
@@ -1136,16 +1302,14 @@ int pair_merge_lds(int dmax) {
     return need;
 }
 
-hipError_t launch_merge_pairs(const Job* J, const Bounds& b, int phase, hipStream_t s) {
-    const int64_t cap = (b.total / kMinTile + (int64_t)b.R * b.ml1) / 2 + 1;
-    // as many workgroups as stay resident (their LDS decides): they stride
-    // over the phase's items, and a phase with none (captured plans launch
-    // every phase up to the bound) costs one round of empty workgroups
-    int64_t per_cu = (160 * 1024) / ((int64_t)b.pair_lds + 4 * (kMergeWinWords + 1));
+hipError_t launch_merge_sched(const Job* J, const Bounds& b, hipStream_t s) {
+    k_merge_plan<<<1, kPlanThreads, 0, s>>>(J);
+    // as many workgroups as stay resident (their LDS decides); each takes
+    // items until none is left, so a call with few items ends quickly
+    int64_t per_cu = (160 * 1024) / ((int64_t)b.pair_lds + 4 * (kMergeWinWords + 8));
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 4) per_cu = 4;
-    const int64_t g = cap < 256 * per_cu ? cap : 256 * per_cu;
-    k_merge_pairs<<<(unsigned)(g < 1 ? 1 : g), kPairThreads, b.pair_lds, s>>>(J, phase);
+    k_merge_sched<<<(unsigned)(256 * per_cu), kPairThreads, b.pair_lds, s>>>(J);
     return hipGetLastError();
 }
 

@@ -3,8 +3,8 @@
 //   k_sort_init   zero the work-list counters
 //   k_tile_plan   one wave per list, four lists per workgroup: key-lane
 //                 offsets of the list's sub-arrays, its odd-even
-//                 transposition tiles and the first merge-split phase's work
-//                 items; list slots are claimed with one global atomic per
+//                 transposition tiles and the sub-arrays merged through HBM;
+//                 list slots are claimed with one global atomic per
 //                 workgroup and record width
 //   k_pack        one wave per 1,024-word chunk: big-endian uint64 key lanes
 //                 (the paper's fixed-width word slots, Section III approach
@@ -13,14 +13,13 @@
 //                 tile pairs of one phase (Baudet and Stevenson, 1978): tiles
 //                 a and a+1, both sorted, are merged in LDS; the lower keeps
 //                 the smaller half.  (The batched form's pair merge is
-//                 k_merge_pairs, with the in-LDS kernels.)
+//                 k_merge_sched, with the in-LDS kernels.)
 #include "bsort_internal.h"
 
 namespace bsort {
 
 __global__ __launch_bounds__(256) void k_sort_init(const Job* __restrict__ J) {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int i0 = threadIdx.x;
     if (i0 < kNumD) J->tile_count[i0] = 0;
     if (i0 < kNumD * kLdsClasses) {
         J->lb_count[i0] = 0;
@@ -29,9 +28,8 @@ __global__ __launch_bounds__(256) void k_sort_init(const Job* __restrict__ J) {
     }
     if (i0 <= kLdsMaxD) J->hc_count[i0] = 0;
     if (i0 == 0) J->pmax[0] = 0;
-    // phase counters in use: every sub-array needs fewer than phase_bound phases
-    const int64_t top = J->phase_bound < J->phase_cap ? J->phase_bound : J->phase_cap;
-    for (int64_t i = i0; i <= top; i += step) J->mcount[i] = 0;
+    if (i0 < 2) J->mcounts[i0] = 0;
+    if (i0 < 3) J->mhead[i0] = 0;
 }
 
 // one wave per list; the workgroup's four waves share one global claim per
@@ -47,8 +45,8 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J, in
     __shared__ int64_t kos[kTileWavesPerBlock][kMaxLen + 1];
     __shared__ int blk_tiles[kNumD];
     __shared__ int64_t blk_tile_base[kNumD];
-    __shared__ int blk_items;
-    __shared__ int64_t blk_item_base;
+    __shared__ int blk_msub, blk_mtiles;
+    __shared__ int64_t blk_msub_base, blk_mtile_base;
     constexpr int kLb = kNumD * kLdsClasses;          // front counts, then back counts
     __shared__ int blk_lb[2 * kLb];
     __shared__ int64_t blk_lb_base[2 * kLb];
@@ -58,7 +56,10 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J, in
     if (tid < kNumD) blk_tiles[tid] = 0;
     if (tid < 2 * kLb) blk_lb[tid] = 0;
     if (tid <= kLdsMaxD) blk_hc[tid] = 0;
-    if (tid == 0) blk_items = 0;
+    if (tid == 0) {
+        blk_msub = 0;
+        blk_mtiles = 0;
+    }
     __syncthreads();
 
     const int r = blockIdx.x * kTileWavesPerBlock + wv;
@@ -74,7 +75,8 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J, in
     // per length L = lane + 64*k (k = 0, 1): route, tiles, tile slot, merge slot.
     // route: 0 none, 1 one register tile, 2 whole sub-array in LDS (class lcls),
     // 3 HBM tiles merged phase by phase
-    int nt[2] = {0, 0}, tslot[2] = {0, 0}, islot[2] = {0, 0}, route[2] = {0, 0}, lcls[2] = {0, 0};
+    int nt[2] = {0, 0}, tslot[2] = {0, 0}, islot[2] = {0, 0}, mtslot[2] = {0, 0};
+    int route[2] = {0, 0}, lcls[2] = {0, 0};
     if (active) {
         int64_t run = (int64_t)wmax * a;    // uint64 offset of each sub-array's lane 0
         for (int k = 0; k < 2; ++k) {
@@ -118,7 +120,8 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J, in
                 if (D <= kLdsMaxD) tslot[k] = atomicAdd(&blk_hc[D], nt[k]);
                 else tslot[k] = atomicAdd(&blk_tiles[D], nt[k]);
                 if (nt[k] >= 2 && !tiles_only) {
-                    islot[k] = atomicAdd(&blk_items, nt[k] / 2);
+                    islot[k] = atomicAdd(&blk_msub, 1);
+                    mtslot[k] = atomicAdd(&blk_mtiles, nt[k]);
                     __hip_atomic_fetch_max(gp(J->pmax), nt[k], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
@@ -128,7 +131,8 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J, in
     __syncthreads();
     if (tid < kNumD && blk_tiles[tid] > 0)
         blk_tile_base[tid] = gadd(J->tile_count + tid, blk_tiles[tid]);
-    if (tid == kNumD && blk_items > 0) blk_item_base = gadd(J->mcount, blk_items);
+    if (tid == kNumD && blk_msub > 0) blk_msub_base = gadd(J->mcounts, blk_msub);
+    if (tid == kNumD + 1 && blk_mtiles > 0) blk_mtile_base = gadd(J->mcounts + 1, blk_mtiles);
     if (tid < 2 * kLb && blk_lb[tid] > 0)
         blk_lb_base[tid] = gadd(tid < kLb ? J->lb_count + tid : J->lb_back + (tid - kLb),
                                 blk_lb[tid]);
@@ -193,25 +197,24 @@ __global__ __launch_bounds__(256) void k_tile_plan(const Job* __restrict__ J, in
             J->tiles[D][base + t] = d;
         }
         if (nt[k] < 2 || tiles_only) continue;
-        const int np = nt[k] / 2;                    // phase 0 pairs (0,1), (2,3), ...
-        const int64_t ib = blk_item_base + islot[k];
-        if (ib + np > J->merge_cap) {
-            set_status(J, ST_OVERFLOW);
-            continue;
-        }
-        for (int q = 0; q < np; ++q) {
-            MergeItem m;
-            m.pos0 = pos0;
-            m.key_off = ko;
-            m.pair_base = 0;
-            m.n_b = nb;
-            m.L = L;
-            m.T = T;
-            m.a = 2 * q;
-            m.p = nt[k];
-            m.s = 0;
-            J->mlist[0][ib + q] = m;
-        }
+        // a sub-array of nt tiles merged through HBM: nt merge-split phases.
+        // Every claimed entry inside the list is written (p = 0, no work, if
+        // its tiles do not fit the tile table), so the merge plan never reads
+        // an entry of an earlier call.
+        const int64_t mi = blk_msub_base + islot[k];
+        const int64_t tb = blk_mtile_base + mtslot[k];
+        const bool fits = tb + nt[k] <= J->mtile_cap;
+        if (mi >= J->msub_cap || !fits) set_status(J, ST_OVERFLOW);
+        if (mi >= J->msub_cap) continue;
+        MSub m;
+        m.pos0 = pos0;
+        m.key_off = ko;
+        m.tile_base = tb;
+        m.n_b = nb;
+        m.L = L;
+        m.T = T;
+        m.p = fits ? nt[k] : 0;
+        J->msub[mi] = m;
     }
 }
 
@@ -413,26 +416,22 @@ hipError_t launch_sort_prep(const Job* J, const Bounds& b, bool after_bucketize,
         hipError_t e = launch_chunk_plan(J, b, false, s);   // k_pack's chunk map
         if (e != hipSuccess) return e;
     }
-    k_sort_init<<<grid_for2((int64_t)b.phase_bound + kNumD + 1, 256, 1024), 256, 0, s>>>(J);
+    k_sort_init<<<1, 256, 0, s>>>(J);
     k_tile_plan<<<grid_for2(b.R, kTileWavesPerBlock, 0x7fffffff), 256, 0, s>>>(
         J, after_bucketize && b.fused_pack ? 0 : 1);
     // keys already written by the scatter when it packs (batched form)
     return b.fused_pack ? hipGetLastError() : launch_pack(J, b, s);
 }
 
-hipError_t launch_merges(const Job* J, const Bounds& b, int phases, hipStream_t s) {
+hipError_t launch_merges(const Job* J, const Bounds& b, hipStream_t s) {
+    if (!b.hbm_merge) return hipSuccess;               // no sub-array can take this path
     for (int D = 2; D <= b.dmax && D <= kLdsMaxD; ++D) {
         if (b.hbm_class[D] < 0) continue;
         hipError_t e = launch_hbm_chunks(J, b, D, s);
         if (e != hipSuccess) return e;
     }
-    if (b.flags & kFlagTilesOnly) return hipSuccess;
-    if (phases < 0 || phases > b.phase_bound) phases = b.phase_bound;
-    for (int ph = 0; ph < phases; ++ph) {
-        hipError_t e = launch_merge_pairs(J, b, ph, s);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if ((b.flags & kFlagTilesOnly) || !b.hbm_merge) return hipSuccess;
+    return launch_merge_sched(J, b, s);
 }
 
 }  // namespace bsort

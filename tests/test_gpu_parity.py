@@ -399,10 +399,78 @@ def test_large_serve_request_merged_through_hbm(bs, ws):
     w = wordgen.serve_request(3, 1_000_000)
     expect = oracle.definition_sort(w.bytes, w.offsets)
     assert np.array_equal(gpu_sort(bs, ws, w, 32), expect)
-    # the same through a two-list batch (phase count read back per call)
+    # the same through a two-list batch
     batch = wordgen.Batch.concat([w, wordgen.serve_request(4, 3000)])
     got = gpu_batch(bs, ws, batch, 32)
     assert np.array_equal(got[:w.n], expect)
+
+
+def _busy_stream(mib=2048, copies=6):
+    """Queue several large device-to-device copies on the current stream, so
+    that it stays busy for milliseconds after this returns."""
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(copies):
+        b.copy_(a)
+    return a, b
+
+
+def test_sort_calls_do_not_block_the_host(bs, ws):
+    """bsort_sort_batch and bsort_sort_buckets on lists whose sub-arrays merge
+    through HBM return while the stream still has the copies queued before
+    them (no host synchronisation inside the calls); the results are exact."""
+    w = wordgen.serve_request(3, 1_000_000)
+    expect = oracle.definition_sort(w.bytes, w.offsets)
+    batch = wordgen.Batch.concat([w, wordgen.serve_request(4, 3000)])
+    b, o = bs.to_device(batch.bytes, batch.offsets)
+    rs = torch.from_numpy(batch.req_start).cuda()
+    bw, ow = bs.to_device(w.bytes, w.offsets)
+    out = torch.empty(batch.total, dtype=torch.int32, device="cuda")
+    ws.ensure(bs.workspace_bytes(batch.total, 32, batch.R))
+    torch.cuda.synchronize()
+    keep = _busy_stream()
+    bs.sort_batch(b, o, rs, batch.req_start, 32, ws=ws, out=out)
+    assert not torch.cuda.current_stream().query(), "sort_batch waited for the stream"
+    bs.check_device_status(ws)
+    assert np.array_equal(out[:w.n].cpu().numpy(), expect)
+    keep = _busy_stream()
+    perm = bs.sort(bw, ow, 32, ws=ws)
+    assert not torch.cuda.current_stream().query(), "bucketize/sort_buckets waited"
+    bs.check_device_status(ws)
+    assert np.array_equal(perm.cpu().numpy(), expect)
+    del keep
+
+
+def test_merge_stall_is_reported(bs, ws):
+    """With the stall test flag every merge-split wait gives up at once: the
+    launch ends and the device status says so; the next call is exact."""
+    w = wordgen.serve_request(3, 1_000_000)
+    b, o = bs.to_device(w.bytes, w.offsets)
+    bs.sort(b, o, 32, tune=bs.tuning(0, 0, bs.FLAG_STALL_TEST), ws=ws)
+    with pytest.raises(bs.BsortError, match="gave up"):
+        bs.check_device_status(ws)
+    perm = bs.sort(b, o, 32, ws=ws)
+    bs.check_device_status(ws)
+    assert np.array_equal(perm.cpu().numpy(), oracle.definition_sort(w.bytes, w.offsets))
+
+
+def test_plan_with_hbm_merges_replays(bs):
+    """A captured plan over lists whose sub-arrays merge through HBM (one
+    merge launch in the graph, its work found on the device), replayed on
+    two batches; each result equals the oracle."""
+    a = wordgen.Batch.concat([wordgen.serve_request(5, 600_000), wordgen.serve_request(6, 5_000)])
+    c = wordgen.Batch.concat([wordgen.serve_request(7, 2_000), wordgen.serve_request(8, 400_000),
+                              wordgen.serve_request(9, 90_000)])
+    plan = bs.Plan(max(a.total, c.total), 3, 600_000, 32)
+    pws = bs.Workspace(plan.workspace_bytes)
+    for batch in (a, c, a):
+        bt, ot = bs.to_device(batch.bytes, batch.offsets)
+        rs = torch.from_numpy(batch.req_start).cuda()
+        perm = plan.execute(bt, ot, rs, batch.req_start, pws)
+        bs.check_device_status(pws)
+        expect = oracle.definition_sort_batch(batch.bytes, batch.offsets, batch.req_start, 16)
+        assert np.array_equal(perm.cpu().numpy(), expect)
+    plan.close()
 
 
 # ------------------------------------------------------------- batches
