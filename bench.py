@@ -108,8 +108,11 @@ def lds_caps_for(D):
     return [c for c in caps if D * 4 * c <= LDS_BYTES]
 
 
-def lds_tile(tuned, cap, D):
-    """Tile size inside an in-LDS sub-array of class capacity cap."""
+def lds_tile(tuned, cap, D, fixed=False):
+    """Tile size inside an in-LDS sub-array of class capacity cap (fixed:
+    the tuned tile itself, BSORT_FLAG_LDS_TILE)."""
+    if fixed:
+        return min(tuned, 512)
     target = 512 if D <= 2 else cap // 16
     t = tuned
     while t < target and t < 512:
@@ -134,7 +137,7 @@ def tile_ce(n, T):
     return full * (T * (T - 1) // 2) + rest * (rest - 1) // 2
 
 
-def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
+def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys, lds_fixed=False):
     """Host-side census of the work the method does on this input, routed as
     the library routes it: per record width D, the compare-exchanges of
     single-tile sub-arrays ('tiles_dD'), of tiles inside in-LDS sub-arrays
@@ -153,7 +156,7 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
     for L in range(1, ml1):
         D = (L + 3) // 4 + 1
         W = (L + 7) // 8
-        T = min(tile_keys, 64 * kmax_for(D), 1024)
+        T = min(tile_keys, 64 * kmax_for(D), 512)
         Th = hbm_chunk(D) if D <= LDS_MAX_D else min(hbm_tile_keys, 64 * kmax_for(D))
         caps = lds_caps_for(D)
         cap = max(caps) if caps else 0
@@ -170,7 +173,7 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys):
             lo = max(lo, c)
             if not len(lds):
                 continue
-            Tc = lds_tile(T, c, D)
+            Tc = lds_tile(T, c, D, lds_fixed)
             l = out.setdefault(f"lds_d{D}_{c}", {"ce": 0, "words": 0, "D": D, "lds_bytes": 0,
                                                  "buckets": 0, "tile": Tc})
             l["buckets"] += int(len(lds))
@@ -272,9 +275,9 @@ def serve_run(sw, args):
     b = sw.batch
     staging = serve.Staging(b.bytes, b.offsets, 32)
     from paper_1407_6603_amd import autotune
-    tile, hbm, src = autotune.lookup(torch.cuda.get_device_name(0), "large4x1M",
-                                     args.tune_cache or autotune.CACHE)
-    ex = serve.GpuExecutor(staging, arena_bytes=16 << 30, streams=3, tune=bs_tuning(tile, hbm))
+    tile, hbm, tflags, src = autotune.lookup("large4x1M", path=args.tune_cache or autotune.CACHE)
+    ex = serve.GpuExecutor(staging, arena_bytes=16 << 30, streams=3,
+                           tune=bs_tuning(tile, hbm, tflags))
 
     def requests(rate):
         return [serve.Request(i, float(sw.arrivals[i]) / rate if rate != float("inf") else 0.0,
@@ -300,7 +303,9 @@ def serve_run(sw, args):
         if st is None:
             st = dict(lst)
             sample_res = res
-    st.update({"tile_keys": tile, "hbm_tile_keys": hbm or "default", "tuning_source": src,
+    st.update({"tile_keys": tile, "hbm_tile_keys": hbm or "default",
+               "lds_tile": "tuned" if tflags & autotune.FLAG_LDS_TILE else "library",
+               "tuning_source": src,
                "offered_words_per_s": float(b.total / max(sw.arrivals[-1], 1e-9)),
                "arena_bytes": ex.arena_bytes,
                "saturation": legs,
@@ -325,9 +330,9 @@ def serve_run(sw, args):
     return st
 
 
-def bs_tuning(tile, hbm):
+def bs_tuning(tile, hbm, flags=0):
     import paper_1407_6603_amd as bs
-    return bs.tuning(tile, 0, 0, hbm)
+    return bs.tuning(tile, 0, flags, hbm)
 
 
 def serve_line(sw, args, gen_s):
@@ -372,17 +377,16 @@ def cu_child(args):
     import torch
     import paper_1407_6603_amd as bs
     from paper_1407_6603_amd import autotune
-    tile, hbm = args.tile, args.hbm_tile
+    tile, hbm, tflags = args.tile, args.hbm_tile, args.tune_flags
     if tile == 0 and hbm == 0:
-        tile, hbm, _ = autotune.lookup(torch.cuda.get_device_name(0), "batch4096",
-                                       args.tune_cache or autotune.CACHE)
+        tile, hbm, tflags, _ = autotune.lookup("batch4096", path=args.tune_cache or autotune.CACHE)
     dev = torch.device("cuda:0")
     total, R, max_len = int(req[-1]), len(req) - 1, 12
     b_t, o_t = bs.to_device(bytes_, offsets, dev)
     rs_t = torch.from_numpy(req).to(dev)
     ws = bs.Workspace(bs.workspace_bytes(total, max_len, R), dev)
     perm = torch.empty(total, dtype=torch.int32, device=dev)
-    tune = bs.tuning(tile, 0, bs.FLAG_SERIAL_STAGES, hbm)
+    tune = bs.tuning(tile, 0, bs.FLAG_SERIAL_STAGES | tflags, hbm)
     timer = bs.StageTimer(max_len)
     bs.sort_batch_staged(b_t, o_t, rs_t, req, max_len, timer, tune, ws, out=perm)
     torch.cuda.synchronize()
@@ -419,7 +423,8 @@ def cu_scaling_run(batch, args):
             env = dict(os.environ)
             env["HSA_CU_MASK"] = f"0:0-{n - 1}"
             cmd = [sys.executable, os.path.abspath(__file__), "--cu-child", "--cu-data", d,
-                   "--tile", str(args.tile), "--hbm-tile", str(args.hbm_tile)]
+                   "--tile", str(args.tile), "--hbm-tile", str(args.hbm_tile),
+                   "--tune-flags", str(args.tune_flags)]
             if args.tune_cache:
                 cmd += ["--tune-cache", args.tune_cache]
             res = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=300)
@@ -448,6 +453,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tile", type=int, default=0, help="tile_keys (0: autotune cache or default)")
+    ap.add_argument("--tune-flags", type=int, default=0,
+                    help="tuning flags with --tile/--hbm-tile (16: BSORT_FLAG_LDS_TILE)")
     ap.add_argument("--hbm-tile", type=int, default=0,
                     help="hbm_tile_keys, the merge-split block width through HBM "
                          "(0: autotune cache or library default)")
@@ -525,19 +532,20 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    tile, hbm_tile, tuned_from = args.tile, args.hbm_tile, "flags"
+    tile, hbm_tile, tflags, tuned_from = args.tile, args.hbm_tile, args.tune_flags, "flags"
     if tile == 0 and hbm_tile == 0:
-        tile, hbm_tile, tuned_from = autotune.lookup(torch.cuda.get_device_name(0), "batch4096",
-                                                     args.tune_cache or autotune.CACHE)
+        tile, hbm_tile, tflags, tuned_from = autotune.lookup(
+            "batch4096", path=args.tune_cache or autotune.CACHE)
 
     b_t, o_t = bs.to_device(batch.bytes, batch.offsets, dev)
     rs_t = torch.from_numpy(batch.req_start).to(dev)
     perm = torch.empty(total, dtype=torch.int32, device=dev)
-    tune = bs.tuning(tile, 0, 0, hbm_tile)
+    tune = bs.tuning(tile, 0, tflags, hbm_tile)
     stream = torch.cuda.current_stream()
     ws = bs.Workspace(bs.workspace_bytes(total, max_len, batch.R), dev)
     struct, merge_bytes, phases_max = workload_structure(
-        batch.offsets, batch.req_start, max_len, tile or 256, 2048)
+        batch.offsets, batch.req_start, max_len, tile or 256, 2048,
+        lds_fixed=bool(tflags & autotune.FLAG_LDS_TILE))
 
     def step(timer):
         bs.sort_batch_staged(b_t, o_t, rs_t, batch.req_start, max_len, timer, tune, ws, out=perm)
@@ -555,7 +563,7 @@ def main():
     serial = None
     sperm = None
     if not args.no_serial:
-        stune = bs.tuning(tile, 0, bs.FLAG_SERIAL_STAGES, hbm_tile)
+        stune = bs.tuning(tile, 0, bs.FLAG_SERIAL_STAGES | tflags, hbm_tile)
         sperm = torch.empty(total, dtype=torch.int32, device=dev)
         reps = min(max(args.steps, 1), 5)
         stimers = [bs.StageTimer(max_len, stream) for _ in range(reps)]
@@ -650,22 +658,34 @@ def main():
         plan.close()
         del gws, gperm
 
-    # ---- the plain form: one launch per (list, length) sub-array and per phase
+    # ---- the plain form: the same kernels, one launch per (list, length)
+    # sub-array and per merge-split phase (plus per-list bucketize launches
+    # and one host read of the sub-array sizes); 3 timed steps with events
     plain = None
     if not args.no_plain:
-        ptune = bs.tuning(tile, 0, bs.FLAG_PER_BUCKET_LAUNCH, hbm_tile)
+        ptune = bs.tuning(tile, 0, bs.FLAG_PER_BUCKET_LAUNCH | tflags, hbm_tile)
         pws = bs.Workspace(bs.workspace_bytes(total, max_len, batch.R), dev)
         pperm = torch.empty(total, dtype=torch.int32, device=dev)
         bs.sort_batch(b_t, o_t, rs_t, batch.req_start, max_len, ptune, pws, out=pperm)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        bs.sort_batch(b_t, o_t, rs_t, batch.req_start, max_len, ptune, pws, out=pperm)
-        torch.cuda.synchronize()
-        plain_s = time.perf_counter() - t1
+        preps = 3
+        pev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        pms = []
+        for _ in range(preps):
+            pev[0].record()
+            bs.sort_batch(b_t, o_t, rs_t, batch.req_start, max_len, ptune, pws, out=pperm)
+            pev[1].record()
+            torch.cuda.synchronize()
+            pms.append(pev[0].elapsed_time(pev[1]))
         bs.check_device_status(pws)
         same = bool(np.array_equal(pperm.cpu().numpy(), got))
-        plain = {"value": total / plain_s, "unit": "words/s", "ms_per_step": plain_s * 1e3,
-                 "identical_to_batched": same}
+        plain_ms = float(np.median(pms))
+        plain = {"value": total / (plain_ms / 1e3), "unit": "words/s", "ms_per_step": plain_ms,
+                 "steps": preps, "ms_each": pms, "identical_to_batched": same,
+                 "kernels": "the batched form's: per-list bucketize with the fused pack; per "
+                            "sub-array k_oets_bucket (one register tile), k_bucket_lds_one (in "
+                            "LDS, or the chunks of a sub-array merged through HBM) and one "
+                            "k_merge_phase_one per merge-split phase"}
         del pws, pperm
 
     # ---- pre-processing leg: the batch's words as one raw text (separators
@@ -825,7 +845,7 @@ def main():
             "unit": "TOP/s", "frac": lds_ce / (lds_span / 1e3) / 1e12 / PEAK_INT32_TOPS}
     elif dom == "merge_split" and merge_bytes:
         achieved = merge_bytes / (dom_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "kernel": "k_merge_pairs", "achieved": achieved,
+        roof = {"bound": "hbm", "kernel": "k_merge_sched", "achieved": achieved,
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                 "traffic": None, "bytes_per_step": merge_bytes}
 
@@ -863,6 +883,7 @@ def main():
                                "vocabulary per list, 5% capitalised",
                    "global_batch": batch.R, "words": total, "max_len": max_len,
                    "tile_keys": tile or 256, "hbm_tile_keys": hbm_tile or "default",
+                   "lds_tile": "tuned" if tflags & autotune.FLAG_LDS_TILE else "library",
                    "tuning_source": tuned_from, "parallelism": "single GPU"},
         "graph_plan": graph,
         "per_bucket_launch": plain,

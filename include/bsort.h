@@ -95,10 +95,10 @@ typedef struct {
 /* Launch tuning; NULL or zero fields mean the library default. */
 typedef struct {
     int32_t tile_keys;       /* words per odd-even transposition tile for sub-arrays sorted
-                                in one tile or in LDS: a power of two in [128, 4096],
-                                clamped to 512 and per key width */
-    int32_t merge_threads;   /* threads per merge-split workgroup of the plain form:
-                                64..1024, multiple of 64 */
+                                in one tile (and in LDS with BSORT_FLAG_LDS_TILE): a power
+                                of two in [128, 4096], clamped to 512 and per key width */
+    int32_t merge_threads;   /* not used (kept for compatibility): 0, or a multiple of
+                                64 in 64..1024 */
     int32_t flags;           /* BSORT_FLAG_* */
     int32_t hbm_tile_keys;   /* tile size for sub-arrays too large for LDS, merged
                                 through HBM: a power of two in [128, 8192].  Default (0):
@@ -107,9 +107,12 @@ typedef struct {
                                 2048 for longer keys; clamped per key width and LDS size */
 } bsort_tuning;
 
-/* The plain form: one kernel launch per (request, length) sub-array and per
- * merge-split phase, with a host synchronisation to read the sub-array
- * sizes.  Same result; for comparison with the batched form. */
+/* The plain form: the batched form's kernels launched one sub-array at a
+ * time -- per list its bucketize launches, then one host synchronisation to
+ * read every sub-array's size, then per (request, length) sub-array one sort
+ * launch (routed as the batched form routes it) and one launch per
+ * merge-split phase.  Same result; for comparison with the batched form.
+ * This form waits for the device inside the call. */
 #define BSORT_FLAG_PER_BUCKET_LAUNCH 1
 /* Testing only: stop after the tile sorts (no merge-split); perm then holds
  * each tile sorted on its own. */
@@ -124,6 +127,12 @@ typedef struct {
  * ends, bsort_get_device_status reports BSORT_E_INVALID ("a wait of the
  * merge-split launch gave up") and perm is unspecified. */
 #define BSORT_FLAG_STALL_TEST 8
+/* Sub-arrays sorted in LDS use tile_keys (clamped to 512 and per key width)
+ * as the size of the tiles they sort before merging.  Without it the tile is
+ * 512 words for keys of up to 4 bytes and, for longer keys, tile_keys doubled
+ * until at most 16 merge-split phases remain (at most 512).  Same result; a
+ * knob for the autotuner. */
+#define BSORT_FLAG_LDS_TILE 16
 
 /* Workspace bytes for up to total_words words in up to n_requests lists with
  * words of at most max_len bytes.  Returns 0 for invalid arguments. */

@@ -21,6 +21,7 @@ FLAG_PER_BUCKET_LAUNCH = 1
 FLAG_TILES_ONLY = 2
 FLAG_SERIAL_STAGES = 4
 FLAG_STALL_TEST = 8
+FLAG_LDS_TILE = 16
 KEY_BYTES, KEY_LENGTH, KEY_LENGTH_BYTES = 0, 1, 2
 LAYOUT_PACKED, LAYOUT_TEXT = 0, 1
 

@@ -20,6 +20,7 @@ FLAG_PER_BUCKET_LAUNCH = _lib.FLAG_PER_BUCKET_LAUNCH
 FLAG_TILES_ONLY = _lib.FLAG_TILES_ONLY
 FLAG_SERIAL_STAGES = _lib.FLAG_SERIAL_STAGES
 FLAG_STALL_TEST = _lib.FLAG_STALL_TEST
+FLAG_LDS_TILE = _lib.FLAG_LDS_TILE
 MAX_LEN = _lib.BSORT_MAX_LEN
 
 

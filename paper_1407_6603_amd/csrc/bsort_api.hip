@@ -31,7 +31,6 @@ bsort_status fail(bsort_status st, const std::string& msg) {
 
 constexpr int kDefaultTile = 256;        // single tiles and in-LDS sub-arrays
 constexpr int kDefaultHbmTile = 2048;    // sub-arrays merged through HBM
-constexpr int kDefaultMergeThreads = 256;
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -113,7 +112,7 @@ bsort_status check_tuning(const bsort_tuning* t) {
         (t->merge_threads < 64 || t->merge_threads > 1024 || t->merge_threads % 64))
         return fail(BSORT_E_INVALID, "merge_threads must be 0 or a multiple of 64 in [64, 1024]");
     if (t->flags & ~(BSORT_FLAG_PER_BUCKET_LAUNCH | BSORT_FLAG_TILES_ONLY |
-                     BSORT_FLAG_SERIAL_STAGES | BSORT_FLAG_STALL_TEST))
+                     BSORT_FLAG_SERIAL_STAGES | BSORT_FLAG_STALL_TEST | BSORT_FLAG_LDS_TILE))
         return fail(BSORT_E_INVALID, "unknown flag");
     return BSORT_OK;
 }
@@ -130,21 +129,15 @@ Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
     b.dmax = L.dmax;
     b.flags = t ? t->flags : 0;
     const int want = (t && t->tile_keys) ? t->tile_keys : kDefaultTile;
-    const int budget = merge_lds_budget();
-    int need = 0;
     int64_t pb = 0;
     for (int D = 2; D <= kMaxD; ++D) {
         // single tiles and tiles inside in-LDS sub-arrays
         int T = std::min(std::min(want, kWave * kmax_for(D)), kLdsMaxTile);
         b.tile_keys[D] = T;
-        // sub-arrays too large for LDS, merged through HBM.  Batched form:
-        // chunks of the largest power of two whose pair fits LDS, sorted by
-        // an in-LDS class (D <= kLdsMaxD), else register-sized tiles.  The
-        // plain form keeps register tiles whose pairs it merges in LDS.
+        // sub-arrays too large for LDS, merged through HBM: chunks of the
+        // largest power of two whose pair fits LDS, sorted by an in-LDS class
+        // (D <= kLdsMaxD), else register-sized tiles
         const int want_h = (t && t->hbm_tile_keys) ? t->hbm_tile_keys : 0;
-        int Tp = std::min(want_h ? want_h : kDefaultHbmTile, kWave * kmax_for(D));
-        while (Tp > kMinTile && D * 2 * Tp * 4 > budget) Tp >>= 1;
-        b.plain_tile_keys[D] = Tp;
         int Th;
         if (D <= kLdsMaxD) {
             Th = hbm_chunk_max(D);
@@ -159,14 +152,9 @@ Bounds make_bounds(const Layout& L, int64_t total, int32_t R, int64_t n_max,
         int cap = 0;                                   // largest in-LDS sub-array for D
         for (int c = 0; c < kLdsClasses; ++c)
             if (lds_fits(D, c)) cap = std::max(cap, lds_cap(c, D));
-        if (n_max > std::max(cap, T)) {                // some sub-array may take the HBM path
-            need = std::max(need, D * 2 * Tp * 4);
+        if (n_max > std::max(cap, T))                  // some sub-array may take the HBM path
             pb = std::max<int64_t>(pb, (n_max + Th - 1) / Th);
-        }
     }
-    b.merge_threads = (t && t->merge_threads) ? t->merge_threads : kDefaultMergeThreads;
-    // twice the inputs when that fits: merged output staged in LDS, written coalesced
-    b.merge_lds = std::max(1024, std::min(budget, 2 * need));
     b.lb_cap = L.lb_cap;
     b.hbm_merge = pb > 1;
     b.pair_lds = pair_merge_lds(L.dmax);
@@ -827,10 +815,13 @@ const char* bsort_version(void) { return "bsort 0.1 gfx950"; }
 
 namespace {
 
-// The plain form: per list, the bucketize launches; one host
-// synchronisation to read every sub-array size; then per list one pack
-// launch and, per sub-array, one tile launch and one launch per merge-split
-// phase.
+// The plain form: the batched form's kernels, launched per list and per
+// sub-array.  Per list, the bucketize launches (the scatter packs the key
+// lanes, as in the batched form); one host synchronisation to read every
+// sub-array's size and key offset; then per (list, length) sub-array one
+// launch routed as the batched plan routes it (one register tile, one in-LDS
+// sort, or the chunk sorts of a sub-array merged through HBM) and, for the
+// last, one launch per merge-split phase.
 bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
                         const Layout& L, char* ws, hipStream_t s) {
     const int32_t R = b->n_requests;
@@ -844,6 +835,7 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
         Layout Lr;
         make_layout(n, 1, L.ml1 - 1, Lr);
         Bounds br = make_bounds(Lr, n, 1, n, t);
+        br.fused_pack = 1;
         Job j = base_job(L, ws, bd0);
         j.bytes = b->bytes;
         j.n_bytes = b->n_bytes;
@@ -860,68 +852,62 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
         j.perm = perm + h[r];
         j.keys = (uint64_t*)(ws + L.keys) + (int64_t)wmax * h[r];
         j.key_off = (int64_t*)(ws + L.key_off) + (int64_t)r * ml1;
-        // each list keeps its own chunk map: its pack runs after every list's bucketize
+        // each list keeps its own chunk map; the chunk histograms are reused
+        // in stream order
         j.chunk_begin = (int64_t*)((char*)&jobs[r] + offsetof(Job, cb_inline));
         j.chunk_cap = Lr.chunk_cap;
+        j.flags |= kJobFusedPack;
         if (r > 0) j.flags |= kJobKeepStatus;
         HIP_TRY(launch_set_job(j, &jobs[r], s));
         br.chunk_cap = Lr.chunk_cap;
         HIP_TRY(launch_bucketize(&jobs[r], br, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
-    std::vector<int32_t> cnt((size_t)R * ml1);
+    std::vector<int32_t> cnt((size_t)R * ml1), st((size_t)R * (ml1 + 1));
+    std::vector<int64_t> ko((size_t)R * ml1);
     HIP_TRY(hipMemcpy(cnt.data(), ws + L.counts, sizeof(int32_t) * cnt.size(),
                       hipMemcpyDeviceToHost));
-    std::vector<int64_t> ko((size_t)R * ml1);
-    for (int32_t r = 0; r < R; ++r) {
-        int64_t run = 0;
-        for (int l = 0; l < ml1; ++l) {
-            ko[(size_t)r * ml1 + l] = run;
-            run += (int64_t)lanes_for_len(l) * cnt[(size_t)r * ml1 + l];
-        }
-    }
-    HIP_TRY(hipMemcpy(ws + L.key_off, ko.data(), sizeof(int64_t) * ko.size(),
-                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(st.data(), ws + L.starts, sizeof(int32_t) * st.size(),
+                      hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ko.data(), ws + L.key_off, sizeof(int64_t) * ko.size(),
+                      hipMemcpyDeviceToHost));
     const bool tiles_only = t && (t->flags & BSORT_FLAG_TILES_ONLY);
     for (int32_t r = 0; r < R; ++r) {
-        const int64_t n = h[r + 1] - h[r];
-        if (n == 0) continue;
-        Layout Lr;
-        make_layout(n, 1, L.ml1 - 1, Lr);
-        Bounds br = make_bounds(Lr, n, 1, n, t);
-        HIP_TRY(launch_pack(&jobs[r], br, s));
-        int64_t start = 0;
-        for (int l = 0; l < ml1; ++l) {
+        if (h[r + 1] == h[r]) continue;
+        for (int l = 1; l < ml1; ++l) {
             const int nb = cnt[(size_t)r * ml1 + l];
-            const int64_t pos0 = start;
-            start += nb;
-            if (l == 0 || nb < 2) continue;
+            if (nb < 2) continue;
+            const int64_t pos0 = st[(size_t)r * (ml1 + 1) + l];
+            const int64_t k0 = ko[(size_t)r * ml1 + l];
             const int D = dwords_for_len(l);
-            const int T = bd0.plain_tile_keys[D];
-            const int nt = (nb + T - 1) / T;
-            TileDesc td;
-            td.pos0 = pos0;
-            td.key_off = ko[(size_t)r * ml1 + l];
-            td.n_b = nb;
-            td.t0 = 0;
-            td.n = 0;
-            td.L = l;
-            HIP_TRY(launch_tile_one_bucket(&jobs[r], D, td, nt, T, nt > 1 && !tiles_only, s));
-            if (nt < 2 || tiles_only) continue;
-            MergeItem m;
-            m.pos0 = pos0;
-            m.key_off = td.key_off;
-            m.n_b = nb;
-            m.L = l;
-            m.T = T;
-            m.a = 0;
-            m.p = nt;
-            m.s = 0;
-            const int lds = std::min(merge_lds_budget(), 2 * D * 2 * T * 4);
-            for (int ph = 0; ph < nt; ++ph) {
-                const int npairs = (nt - (ph & 1)) / 2;
-                HIP_TRY(launch_merge_one_bucket(&jobs[r], m, npairs, ph, bd0.merge_threads, lds, s));
+            int c = -1;
+            if (nb > bd0.tile_keys[D])
+                for (int q = 0; q < kLdsClasses && c < 0; ++q)
+                    if (lds_fits(D, q) && nb <= lds_cap(q, D)) c = q;
+            if (nb <= bd0.tile_keys[D]) {                  // one register tile
+                TileDesc td{pos0, k0, nb, 0, nb, l};
+                HIP_TRY(launch_tile_one_bucket(&jobs[r], D, td, 1, nb, false, s));
+                continue;
             }
+            if (c >= 0) {                                  // the whole sub-array in LDS
+                LBucket lb{pos0, k0, nb, l, nb, 0};
+                HIP_TRY(launch_lds_one(&jobs[r], D, c, lb, 1, 0, s));
+                continue;
+            }
+            // merged through HBM: chunks (in LDS, or register tiles), then phases
+            const int T = bd0.hbm_tile_keys[D];
+            const int nt = (nb + T - 1) / T;
+            if (D <= kLdsMaxD && bd0.hbm_class[D] >= 0) {
+                LBucket lb{pos0, k0, nb, l, nb, 1};
+                HIP_TRY(launch_lds_one(&jobs[r], D, bd0.hbm_class[D], lb, nt, T, s));
+            } else {
+                TileDesc td{pos0, k0, nb, 0, 0, l};
+                HIP_TRY(launch_tile_one_bucket(&jobs[r], D, td, nt, T, nt > 1 && !tiles_only, s));
+            }
+            if (nt < 2 || tiles_only) continue;
+            MSub m{pos0, k0, 0, nb, l, T, nt};
+            for (int ph = 0; ph < nt; ++ph)
+                HIP_TRY(launch_merge_phase_one(&jobs[r], m, ph, bd0.pair_lds, s));
         }
     }
     return BSORT_OK;

@@ -47,6 +47,7 @@ constexpr int kChunk = kWave * kChunkRounds;   // words per bucketize chunk
 constexpr int kTileWavesPerBlock = 4;
 constexpr int kMinTile = 128;             // 64 lanes x 2 records
 constexpr int kFlagTilesOnly = 2;         // same value as BSORT_FLAG_TILES_ONLY
+constexpr int kFlagLdsTile = 16;          // same value as BSORT_FLAG_LDS_TILE
 // Job.flags: leave the status word as it is
 constexpr int kJobKeepStatus = 1 << 8;
 // Job.flags: the scatter by length also packs each word's key lanes and index
@@ -150,17 +151,6 @@ struct LBucket {             // a sub-array (or a chunk of one) sorted entirely 
     int32_t L;               // word length
     int32_t stride;          // lane stride of the key layout (the whole sub-array's size)
     int32_t wk;              // nonzero: write the sorted keys back (a chunk merged later)
-};
-
-struct MergeItem {           // plain form: merge-split of tiles a and a+1 of a bucket
-    int64_t pos0;
-    int64_t key_off;
-    int32_t n_b;
-    int32_t L;
-    int32_t T;               // tile size of this bucket
-    int32_t a;               // lower tile
-    int32_t p;               // tiles in the bucket
-    int32_t s;               // phase
 };
 
 struct MSub {                // a sub-array merged through HBM (batched form)
@@ -343,13 +333,10 @@ struct Bounds {              // launch sizes fixed on the host (capacities)
     int64_t tile_cap;        // tile list capacity per record width
     int32_t dmax;            // widest record in use
     int32_t hbm_merge;       // some sub-array may be merged through HBM (launch the merges)
-    int32_t merge_threads;   // plain form's merge workgroup size
-    int32_t merge_lds;       // plain form's dynamic LDS bytes per merge workgroup
     int32_t pair_lds;        // dynamic LDS bytes of the batched pair merge
     int32_t tile_keys[kNumD];
     int32_t hbm_tile_keys[kNumD];
     int32_t hbm_class[kNumD];   // in-LDS class sorting HBM chunks of width D (-1: tiles)
-    int32_t plain_tile_keys[kNumD];   // plain form: tiles of sub-arrays merged through HBM
     int32_t fused_pack;      // the scatter packs keys (kJobFusedPack); no k_pack launch
     int64_t lb_cap;
     int32_t flags;
@@ -390,13 +377,15 @@ hipError_t launch_layout_oets(const uint8_t* bytes, int64_t n_bytes, const int64
 size_t tok_workspace_bytes(int64_t n_bytes);
 hipError_t launch_tokenize(const uint8_t* text, int64_t n_bytes, uint8_t* out, int64_t* offsets,
                            int64_t cap_words, int64_t* result, void* ws, hipStream_t s);
-// plain per-bucket form pieces
+// plain per-bucket form pieces: one in-LDS sort of one sub-array (nchunks = 1,
+// chunk = 0) or of the nchunks chunks of chunk words of one sub-array merged
+// through HBM; one merge-split phase of one such sub-array
+hipError_t launch_lds_one(const Job* J, int D, int c, const LBucket& bk, int nchunks, int chunk,
+                          hipStream_t s);
+hipError_t launch_merge_phase_one(const Job* J, const MSub& m, int phase, int lds_bytes,
+                                  hipStream_t s);
 hipError_t launch_pack(const Job* J, const Bounds& b, hipStream_t s);
 hipError_t launch_tile_one_bucket(const Job* J, int D, const TileDesc& first, int ntiles,
                                   int T, bool write_keys, hipStream_t s);
-hipError_t launch_merge_one_bucket(const Job* J, const MergeItem& item0, int npairs,
-                                   int phase, int merge_threads, int lds, hipStream_t s);
-// dynamic LDS a merge workgroup may use on this device (bytes)
-int merge_lds_budget();
 
 }  // namespace bsort

@@ -796,16 +796,106 @@ __device__ __forceinline__ void lds_merge_all(uint32_t* lds, int n, int T, int l
     }
 }
 
+// One sub-array (or chunk) bk, n <= CAP words, sorted by one workgroup in
+// LDS: load, tile sorts, merge-split phases, write back.  Ends with a
+// barrier, so the LDS can take the next entry.
+template <int D, int NT, int CAP>
+__device__ __forceinline__ void lds_sort_entry(const Job* __restrict__ J, const LBucket& bk,
+                                               uint32_t* lds, int* mwin, int T, int logT,
+                                               bool tiles_only, int tid) {
+    constexpr int NW = NT / kWave;
+    constexpr int Dk = D - 1, W = (Dk + 1) / 2;
+    constexpr int KCAP = kmax_for(D) < kLdsMaxTile / kWave ? kmax_for(D) : kLdsMaxTile / kWave;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int n = bk.n_b;                              // n <= CAP (checked when listed)
+    const int64_t ks = bk.stride;                      // key lane stride
+    const gptr<uint64_t> keys = gp(J->keys) + bk.key_off;
+    const gptr<int32_t> perm = gp(J->perm) + bk.pos0;
+    // 5- and 6-byte words whose keys are not written back: a record is
+    // the two key dwords with the word's position (n <= CAP < 2^16) in
+    // the zero low half of the second, compared whole; the index plane
+    // keeps input order and is read at that position at the end
+    const bool full2 = D == 3 && bk.L <= 6 && !bk.wk;    // uniform
+    // 1- and 2-byte words likewise: one dword, the key's high half and
+    // the position (n <= CAP <= 2^16) in the zero low half
+    const bool full1 = D == 2 && bk.L <= 2 && !bk.wk;    // uniform
+#pragma unroll 4
+    for (int i = tid; i < n; i += NT) {
+        const int a = lsw(i);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t v = keys[w * ks + i];
+            lds[(2 * w) * CAP + a] = (uint32_t)(v >> 32) | (full1 ? i : 0);
+            if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + a] = (uint32_t)v | (full2 ? i : 0);
+        }
+        lds[Dk * CAP + a] = (uint32_t)perm[i];     // index plane (unused by full1/2 sorts)
+    }
+    __syncthreads();
+    const int p = (n + T - 1) / T;
+    for (int t = wv; t < p; t += NW) {
+        const int t0 = t * T;
+        const int tn = n - t0 < T ? n - t0 : T;
+        LdsTile src{lds, CAP, t0, tn};
+        if constexpr (D == 3) {
+            if (full2) {
+                sort_tile_full2_k<2, KCAP>(src, tn, lane, (tn + kWave - 1) / kWave);
+                continue;
+            }
+        }
+        if constexpr (D == 2) {
+            if (full1) {
+                sort_tile_full1_k<2, KCAP>(src, tn, lane, (tn + kWave - 1) / kWave);
+                continue;
+            }
+        }
+        sort_tile_any<D, KCAP>(src, tn, lane);
+    }
+    __syncthreads();
+    if constexpr (D == 3) {
+        if (full2) {
+            if (!tiles_only) lds_merge_all<2, NT, CAP, true>(lds, n, T, logT, p, tid, mwin);
+            // each output's index from the index plane, at the position
+            // the record carries (that plane is never written while sorting)
+            for (int i = tid; i < n; i += NT)
+                perm[i] = (int32_t)lds[2 * CAP + lsw((int)(lds[CAP + lsw(i)] & 0xFFFFu))];
+            __syncthreads();                       // LDS reused by the next sub-array
+            return;
+        }
+    }
+    if constexpr (D == 2) {
+        if (full1) {
+            if (!tiles_only) lds_merge_all<1, NT, CAP, true>(lds, n, T, logT, p, tid, mwin);
+            // each output's index from the index plane, at the position
+            // the record carries (that plane is never written while sorting)
+            for (int i = tid; i < n; i += NT)
+                perm[i] = (int32_t)lds[CAP + lsw((int)(lds[lsw(i)] & 0xFFFFu))];
+            __syncthreads();                       // LDS reused by the next sub-array
+            return;
+        }
+    }
+    if (!tiles_only) lds_merge_all<D, NT, CAP>(lds, n, T, logT, p, tid, mwin);
+    for (int i = tid; i < n; i += NT) {
+        const int a = lsw(i);
+        perm[i] = (int32_t)lds[Dk * CAP + a];
+        if (bk.wk) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint64_t hi = lds[(2 * w) * CAP + a];
+                const uint64_t lo = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP + a] : 0u;
+                keys[w * ks + i] = (hi << 32) | lo;
+            }
+        }
+    }
+    __syncthreads();                                   // LDS reused by the next sub-array
+}
+
 template <int D, int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, int list) {
     __shared__ uint32_t lds[D * CAP];
     __shared__ int mwin[1];                            // (window tables: pair merges only)
-    constexpr int NW = NT / kWave;
-    constexpr int Dk = D - 1, W = (Dk + 1) / 2;
-    constexpr int KCAP = kmax_for(D) < kLdsMaxTile / kWave ? kmax_for(D) : kLdsMaxTile / kWave;
     static_assert(D * CAP * 4 <= kLdsBytes, "sub-array does not fit the LDS budget");
     static_assert(CAP % 64 == 0, "lsw permutes whole rows of 64 records");
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x;
     // list < kLdsClasses: the sub-arrays of that size class; list ==
     // kLdsClasses: chunks of sub-arrays that are merged through HBM next
     // a size class's list: entries [0, front) from the front, the rest from
@@ -829,7 +919,8 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
     }
     __shared__ int next_entry;
     const bool tiles_only = (J->flags & kFlagTilesOnly) != 0;
-    const int T = tiles_only ? J->tile_keys[D] : lds_tile(J->tile_keys[D], CAP, D);
+    const bool fixed = tiles_only || (J->flags & kFlagLdsTile);
+    const int T = fixed ? J->tile_keys[D] : lds_tile(J->tile_keys[D], CAP, D);
     const int logT = 31 - __builtin_clz(T);               // tile sizes are powers of two
     for (int64_t it = 0;; ++it) {
         int64_t bi;
@@ -846,87 +937,30 @@ __global__ __launch_bounds__(NT) void k_bucket_lds(const Job* __restrict__ J, in
         }
         if (bi >= cnt) break;
         const LBucket bk = lst[bi < front ? bi : J->lb_cap - 1 - (bi - front)];
-        const int n = bk.n_b;                          // n <= CAP (checked when listed)
-        const int64_t ks = bk.stride;                  // key lane stride
-        const gptr<uint64_t> keys = gp(J->keys) + bk.key_off;
-        const gptr<int32_t> perm = gp(J->perm) + bk.pos0;
-        // 5- and 6-byte words whose keys are not written back: a record is
-        // the two key dwords with the word's position (n <= CAP < 2^16) in
-        // the zero low half of the second, compared whole; the index plane
-        // keeps input order and is read at that position at the end
-        const bool full2 = D == 3 && bk.L <= 6 && !bk.wk;    // uniform
-        // 1- and 2-byte words likewise: one dword, the key's high half and
-        // the position (n <= CAP <= 2^16) in the zero low half
-        const bool full1 = D == 2 && bk.L <= 2 && !bk.wk;    // uniform
-#pragma unroll 4
-        for (int i = tid; i < n; i += NT) {
-            const int a = lsw(i);
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const uint64_t v = keys[w * ks + i];
-                lds[(2 * w) * CAP + a] = (uint32_t)(v >> 32) | (full1 ? i : 0);
-                if (2 * w + 1 < Dk) lds[(2 * w + 1) * CAP + a] = (uint32_t)v | (full2 ? i : 0);
-            }
-            lds[Dk * CAP + a] = (uint32_t)perm[i];     // index plane (unused by full1/2 sorts)
-        }
-        __syncthreads();
-        const int p = (n + T - 1) / T;
-        for (int t = wv; t < p; t += NW) {
-            const int t0 = t * T;
-            const int tn = n - t0 < T ? n - t0 : T;
-            LdsTile src{lds, CAP, t0, tn};
-            if constexpr (D == 3) {
-                if (full2) {
-                    sort_tile_full2_k<2, KCAP>(src, tn, lane, (tn + kWave - 1) / kWave);
-                    continue;
-                }
-            }
-            if constexpr (D == 2) {
-                if (full1) {
-                    sort_tile_full1_k<2, KCAP>(src, tn, lane, (tn + kWave - 1) / kWave);
-                    continue;
-                }
-            }
-            sort_tile_any<D, KCAP>(src, tn, lane);
-        }
-        __syncthreads();
-        if constexpr (D == 3) {
-            if (full2) {
-                if (!tiles_only) lds_merge_all<2, NT, CAP, true>(lds, n, T, logT, p, tid, mwin);
-                // each output's index from the index plane, at the position
-                // the record carries (that plane is never written while sorting)
-                for (int i = tid; i < n; i += NT)
-                    perm[i] = (int32_t)lds[2 * CAP + lsw((int)(lds[CAP + lsw(i)] & 0xFFFFu))];
-                __syncthreads();                       // LDS reused by the next sub-array
-                continue;
-            }
-        }
-        if constexpr (D == 2) {
-            if (full1) {
-                if (!tiles_only) lds_merge_all<1, NT, CAP, true>(lds, n, T, logT, p, tid, mwin);
-                // each output's index from the index plane, at the position
-                // the record carries (that plane is never written while sorting)
-                for (int i = tid; i < n; i += NT)
-                    perm[i] = (int32_t)lds[CAP + lsw((int)(lds[lsw(i)] & 0xFFFFu))];
-                __syncthreads();                       // LDS reused by the next sub-array
-                continue;
-            }
-        }
-        if (!tiles_only) lds_merge_all<D, NT, CAP>(lds, n, T, logT, p, tid, mwin);
-        for (int i = tid; i < n; i += NT) {
-            const int a = lsw(i);
-            perm[i] = (int32_t)lds[Dk * CAP + a];
-            if (bk.wk) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const uint64_t hi = lds[(2 * w) * CAP + a];
-                    const uint64_t lo = 2 * w + 1 < Dk ? lds[(2 * w + 1) * CAP + a] : 0u;
-                    keys[w * ks + i] = (hi << 32) | lo;
-                }
-            }
-        }
-        __syncthreads();                               // LDS reused by the next sub-array
+        lds_sort_entry<D, NT, CAP>(J, bk, lds, mwin, T, logT, tiles_only, tid);
     }
+}
+
+// Plain per-bucket form: one launch for one sub-array sorted in LDS (one
+// workgroup), or for the nchunks chunks of one sub-array merged through HBM
+// (workgroup b takes chunk b: words [b*C, min(n, (b+1)*C)) of the
+// sub-array), with the batched form's per-entry sort.
+template <int D, int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_bucket_lds_one(const Job* __restrict__ J, LBucket bk,
+                                                       int chunk) {
+    __shared__ uint32_t lds[D * CAP];
+    __shared__ int mwin[1];
+    const bool tiles_only = (J->flags & kFlagTilesOnly) != 0;
+    const bool fixed = tiles_only || (J->flags & kFlagLdsTile);
+    const int T = fixed ? J->tile_keys[D] : lds_tile(J->tile_keys[D], CAP, D);
+    const int logT = 31 - __builtin_clz(T);
+    if (chunk > 0) {                                   // chunks of a sub-array merged later
+        const int64_t c0 = (int64_t)blockIdx.x * chunk;
+        bk.pos0 += c0;
+        bk.key_off += c0;
+        bk.n_b = bk.stride - c0 < chunk ? (int)(bk.stride - c0) : chunk;
+    }
+    lds_sort_entry<D, NT, CAP>(J, bk, lds, mwin, T, logT, tiles_only, threadIdx.x);
 }
 
 template <int D>
@@ -989,6 +1023,32 @@ static const LdsLauncher kLdsLaunchers[kLdsMaxD + 1][kLdsClasses] = {
     {}, {}, BSORT_LDS_ROW(2), BSORT_LDS_ROW(3), BSORT_LDS_ROW(4), BSORT_LDS_ROW(5),
     BSORT_LDS_ROW(6), BSORT_LDS_ROW(7), BSORT_LDS_ROW(8), BSORT_LDS_ROW(9)};
 #undef BSORT_LDS_ROW
+
+template <int D, int C>
+static void launch_lds_one_t(const Job* J, const LBucket& bk, int nchunks, int chunk,
+                             hipStream_t s) {
+    if constexpr (lds_fits(D, C))
+        k_bucket_lds_one<D, lds_threads(C, D), lds_cap(C, D)>
+            <<<(unsigned)nchunks, lds_threads(C, D), 0, s>>>(J, bk, chunk);
+}
+
+using LdsOneLauncher = void (*)(const Job*, const LBucket&, int, int, hipStream_t);
+#define BSORT_LDS_ONE_ROW(D) \
+    {launch_lds_one_t<D, 0>, launch_lds_one_t<D, 1>, launch_lds_one_t<D, 2>, \
+     launch_lds_one_t<D, 3>, launch_lds_one_t<D, 4>}
+static const LdsOneLauncher kLdsOneLaunchers[kLdsMaxD + 1][kLdsClasses] = {
+    {}, {}, BSORT_LDS_ONE_ROW(2), BSORT_LDS_ONE_ROW(3), BSORT_LDS_ONE_ROW(4),
+    BSORT_LDS_ONE_ROW(5), BSORT_LDS_ONE_ROW(6), BSORT_LDS_ONE_ROW(7), BSORT_LDS_ONE_ROW(8),
+    BSORT_LDS_ONE_ROW(9)};
+#undef BSORT_LDS_ONE_ROW
+
+hipError_t launch_lds_one(const Job* J, int D, int c, const LBucket& bk, int nchunks, int chunk,
+                          hipStream_t s) {
+    if (D < 2 || D > kLdsMaxD || c < 0 || c >= kLdsClasses || !lds_fits(D, c) || nchunks < 1)
+        return hipErrorInvalidValue;
+    kLdsOneLaunchers[D][c](J, bk, nchunks, chunk, s);
+    return hipGetLastError();
+}
 
 hipError_t launch_lds_class(const Job* J, const Bounds& b, int D, int c, hipStream_t s) {
     if (D < 2 || D > kLdsMaxD || c < 0 || c >= kLdsClasses) return hipErrorInvalidValue;
@@ -1289,14 +1349,34 @@ __global__ __launch_bounds__(kPairThreads) void k_merge_sched(const Job* __restr
     }
 }
 
+// Plain per-bucket form: phase s of sub-array m, workgroup b merging the
+// pair whose lower tile is s%2 + 2b (the batched form's pair merge).
+__global__ __launch_bounds__(kPairThreads) void k_merge_phase_one(const Job* __restrict__ J,
+                                                                  MSub m, int s) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int sflag;
+    __shared__ int mwin[kMergeWinWords];
+    const int t = (s & 1) + 2 * (int)blockIdx.x;
+    if (t + 1 >= m.p) return;                          // uniform
+    merge_pair_d<2>(J, m, t, lds, &sflag, mwin, threadIdx.x, dwords_for_len(m.L));
+}
+
+hipError_t launch_merge_phase_one(const Job* J, const MSub& m, int phase, int lds_bytes,
+                                  hipStream_t s) {
+    const int pairs = (m.p - (phase & 1)) / 2;
+    if (pairs <= 0) return hipSuccess;
+    k_merge_phase_one<<<(unsigned)pairs, kPairThreads, lds_bytes, s>>>(J, m, phase);
+    return hipGetLastError();
+}
+
 int pair_merge_lds(int dmax) {
     int need = 0;
     for (int D = 2; D <= dmax && D <= kMaxD; ++D) need = std::max(need, pair_cap(D) * 4 * D);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_merge_sched,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  kLdsBytes - 4 * (kMergeWinWords + 1));
+        for (const void* f : {(const void*)k_merge_sched, (const void*)k_merge_phase_one})
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      kLdsBytes - 4 * (kMergeWinWords + 1));
         attr = true;
     }
     return need;

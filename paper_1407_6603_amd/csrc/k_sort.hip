@@ -9,11 +9,6 @@
 //   k_pack        one wave per 1,024-word chunk: big-endian uint64 key lanes
 //                 (the paper's fixed-width word slots, Section III approach
 //                 two) and the initial index payload
-//   k_merge_bucket the plain per-bucket form's merge-split of one sub-array's
-//                 tile pairs of one phase (Baudet and Stevenson, 1978): tiles
-//                 a and a+1, both sorted, are merged in LDS; the lower keeps
-//                 the smaller half.  (The batched form's pair merge is
-//                 k_merge_sched, with the in-LDS kernels.)
 #include "bsort_internal.h"
 
 namespace bsort {
@@ -264,117 +259,6 @@ __global__ __launch_bounds__(256) void k_pack(const Job* __restrict__ J) {
     }
 }
 
-// record x > record y, records as SoA dwords in LDS (dword d at lds[d*tot + i])
-__device__ __forceinline__ bool lds_gt(const uint32_t* lds, int tot, int D, int x, int y) {
-    for (int d = 0; d < D; ++d) {
-        const uint32_t u = lds[d * tot + x], v = lds[d * tot + y];
-        if (u != v) return u > v;
-    }
-    return false;
-}
-
-// Merge-split of tiles m.a and m.a+1 of one sub-array, in place.  Both tiles
-// are loaded into LDS; each thread merges a contiguous run of outputs found
-// by a merge-path search; outputs are staged in LDS and written back
-// coalesced when 2*D*(words) dwords fit in lds_dwords, else written directly.
-__device__ void merge_pair(const Job* __restrict__ J, const MergeItem& m, bool last_phase,
-                           uint32_t* lds, int lds_dwords, int* sflag) {
-    const int D = dwords_for_len(m.L), Dk = D - 1, W = lanes_for_len(m.L);
-    const int64_t lo = (int64_t)m.a * m.T;
-    const int na = m.T;
-    const int rest = m.n_b - (m.a + 1) * m.T;
-    const int nb = rest < m.T ? rest : m.T;
-    const int tot = na + nb;
-    uint64_t* keys = J->keys + m.key_off;
-    int32_t* perm = J->perm + m.pos0;
-    const int64_t nbk = m.n_b;
-    const int tid = threadIdx.x, NT = blockDim.x;
-
-    // already in order across the seam?  then nothing moves
-    if (tid == 0) {
-        int in_order = -1;
-        const int64_t ja = lo + na - 1, jb = lo + na;
-        for (int w = 0; w < W && in_order < 0; ++w) {
-            const uint64_t x = keys[w * nbk + ja], y = keys[w * nbk + jb];
-            if (x != y) in_order = x < y;
-        }
-        if (in_order < 0) in_order = perm[ja] < perm[jb];
-        *sflag = in_order;
-    }
-    __syncthreads();
-    if (*sflag != 0) return;                         // uniform
-
-    for (int i = tid; i < tot; i += NT) {
-        const int64_t j = lo + i;
-        for (int w = 0; w < W; ++w) {
-            const uint64_t v = keys[w * nbk + j];
-            lds[(2 * w) * tot + i] = (uint32_t)(v >> 32);
-            if (2 * w + 1 < Dk) lds[(2 * w + 1) * tot + i] = (uint32_t)v;
-        }
-        lds[Dk * tot + i] = (uint32_t)perm[j];
-    }
-    __syncthreads();
-
-    const bool staged = 2 * D * tot <= lds_dwords;
-    uint32_t* outb = lds + D * tot;
-    const int E = (tot + NT - 1) / NT;
-    const int k0 = tid * E;
-    if (k0 < tot) {
-        const int k1 = k0 + E < tot ? k0 + E : tot;
-        // merge path: how many of the first k0 outputs come from tile a
-        int lo_i = k0 - nb > 0 ? k0 - nb : 0;
-        int hi_i = k0 < na ? k0 : na;
-        while (lo_i < hi_i) {
-            const int mid = (lo_i + hi_i) >> 1;
-            if (lds_gt(lds, tot, D, na + (k0 - 1 - mid), mid)) lo_i = mid + 1;
-            else hi_i = mid;
-        }
-        int ia = lo_i, ib = k0 - lo_i;
-        for (int k = k0; k < k1; ++k) {
-            const bool take_a = ib >= nb || (ia < na && lds_gt(lds, tot, D, na + ib, ia));
-            const int src = take_a ? ia++ : na + ib++;
-            if (staged) {
-                for (int d = 0; d < D; ++d) outb[d * tot + k] = lds[d * tot + src];
-            } else {
-                const int64_t jo = lo + k;
-                if (!last_phase) {
-                    for (int w = 0; w < W; ++w) {
-                        const uint64_t hi = lds[(2 * w) * tot + src];
-                        const uint64_t lw = (2 * w + 1 < Dk) ? lds[(2 * w + 1) * tot + src] : 0u;
-                        keys[w * nbk + jo] = (hi << 32) | lw;
-                    }
-                }
-                perm[jo] = (int32_t)lds[Dk * tot + src];
-            }
-        }
-    }
-    if (staged) {
-        __syncthreads();
-        for (int k = tid; k < tot; k += NT) {
-            const int64_t jo = lo + k;
-            if (!last_phase) {
-                for (int w = 0; w < W; ++w) {
-                    const uint64_t hi = outb[(2 * w) * tot + k];
-                    const uint64_t lw = (2 * w + 1 < Dk) ? outb[(2 * w + 1) * tot + k] : 0u;
-                    keys[w * nbk + jo] = (hi << 32) | lw;
-                }
-            }
-            perm[jo] = (int32_t)outb[Dk * tot + k];
-        }
-    }
-}
-
-
-// plain form: one launch per (sub-array, phase); block x takes pair a = (s&1) + 2x
-__global__ __launch_bounds__(1024) void k_merge_bucket(const Job* __restrict__ J, MergeItem m,
-                                                       int s, int lds_dwords) {
-    extern __shared__ uint32_t lds[];
-    __shared__ int sflag;
-    m.a = (s & 1) + 2 * (int)blockIdx.x;
-    if (m.a + 1 >= m.p) return;
-    merge_pair(J, m, s == m.p - 1, lds, lds_dwords, &sflag);
-}
-
 static inline unsigned grid_for2(int64_t items, int per_block, int64_t cap) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g > cap) g = cap;
@@ -382,32 +266,8 @@ static inline unsigned grid_for2(int64_t items, int per_block, int64_t cap) {
     return (unsigned)g;
 }
 
-int merge_lds_budget() {
-    static int budget = -1;
-    if (budget < 0) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-                hipSuccess || v <= 0)
-            v = 64 * 1024;
-        v -= 1024;                                   // room for the static __shared__ words
-        if (v > 160 * 1024) v = 160 * 1024;
-        budget = v;
-        (void)hipFuncSetAttribute((const void*)k_merge_bucket,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, budget);
-    }
-    return budget;
-}
-
 hipError_t launch_pack(const Job* J, const Bounds& b, hipStream_t s) {
     k_pack<<<grid_for2(b.chunk_cap, kTileWavesPerBlock, 0x7fffffff), 256, 0, s>>>(J);
-    return hipGetLastError();
-}
-
-hipError_t launch_merge_one_bucket(const Job* J, const MergeItem& item0, int npairs, int phase,
-                                   int merge_threads, int lds, hipStream_t s) {
-    if (npairs <= 0) return hipSuccess;
-    k_merge_bucket<<<npairs, merge_threads, lds, s>>>(J, item0, phase, lds / 4);
     return hipGetLastError();
 }
 

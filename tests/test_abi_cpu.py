@@ -45,6 +45,25 @@ def test_exports_every_declared_symbol(built):
     assert not missing, f"declared but not exported: {missing}"
 
 
+def test_probe_library_exports_its_header():
+    hdr = os.path.join(ROOT, "include", "bsort_probe.h")
+    lib = os.path.join(ROOT, "paper_1407_6603_amd", "libbsort_probe.so")
+    if not os.path.exists(lib):
+        from paper_1407_6603_amd import build
+        build.build()
+    src = re.sub(r"/\*.*?\*/", "", open(hdr).read(), flags=re.S)
+    declared = sorted(set(re.findall(r"\b(bsort_[a-z_]+)\s*\(", src)))
+    out = subprocess.run(["nm", "-D", "--defined-only", lib], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\sT\s(\S+)", out))
+    assert declared and all(n in exported for n in declared)
+    from paper_1407_6603_amd import probe
+    assert sorted(probe.EXPORTS) == declared
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only",
+                    f"-I{os.path.dirname(hdr)}", "-x", "c", "-"], check=True,
+                   input=b'#include "bsort_probe.h"\nint main(void){return 0;}\n')
+
+
 def test_binding_declares_every_symbol():
     from paper_1407_6603_amd import _lib
     assert sorted(_lib.EXPORTS) == declared_functions()

@@ -231,6 +231,26 @@ def test_zero_one_exhaustive(bs, ws):
     assert np.array_equal(got, zero_one_expect(seqs))
 
 
+def test_zero_one_exhaustive_15_to_20(bs, ws):
+    """The 0/1 principle continued: every 0/1 sequence of length 15..20
+    (2,064,384 sequences, 40.9 M words), sorted as lists of one-byte words,
+    65,536 lists per batch.  The expected order of a 0/1 list is the stable
+    partition: the zeros' indices, then the ones'."""
+    chunk = 1 << 16
+    for n in range(15, 21):
+        shifts = np.arange(n - 1, -1, -1, dtype=np.int64)
+        for v0 in range(0, 1 << n, chunk):
+            v = np.arange(v0, min(v0 + chunk, 1 << n), dtype=np.int64)
+            bits = ((v[:, None] >> shifts) & 1).astype(np.uint8)
+            m = len(v)
+            batch = wordgen.Batch((bits.ravel() + ord("0")).astype(np.uint8),
+                                  np.arange(m * n + 1, dtype=np.int64),
+                                  np.arange(0, m * n + 1, n, dtype=np.int64))
+            got = gpu_batch(bs, ws, batch, 1, tune=bs.tuning(128, 64))
+            expect = np.argsort(bits, axis=1, kind="stable").astype(np.int32).ravel()
+            assert np.array_equal(got, expect), f"n={n}, sequences {v0}..{v0 + m - 1}"
+
+
 @pytest.mark.parametrize("T", [128, 256])
 def test_zero_one_merge_seams(bs, ws, T):
     """Random 0/1 lists whose sizes sit on tile seams: the merge-split
