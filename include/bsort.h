@@ -322,6 +322,28 @@ bsort_status bsort_plan_execute(bsort_plan *plan, const bsort_batch *b, int32_t 
                                 void *ws, size_t ws_bytes, bsort_stream_t stream);
 void bsort_plan_destroy(bsort_plan *plan);
 
+/*
+ * bsort_sort_batch for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * workspace is a static device array of BSORT_STATIC_SCRATCH_BYTES (64 MiB)
+ * per GPU, which the library holds from its first use on that GPU
+ * until the process ends, so the call takes no workspace argument and
+ * allocates nothing (no hipMalloc, no library stream: its stages run in
+ * order on the caller's stream, as with BSORT_FLAG_SERIAL_STAGES).  The
+ * caller passes the batch and perm as for bsort_sort_batch.
+ *   status  device uint32 (may be NULL): written by the call's stream work
+ *           with the device status word (0: no fault; otherwise the bits
+ *           that bsort_get_device_status decodes)
+ * Returns BSORT_E_WORKSPACE, launching nothing, when the batch needs more
+ * scratch than the array holds (bsort_workspace_bytes(total, max_len, R) >
+ * BSORT_STATIC_SCRATCH_BYTES), and BSORT_E_INVALID for the per-bucket
+ * form.  Every call on one GPU uses the same array: calls that overlap on a
+ * GPU (two streams, two threads) race and must be ordered by the caller.
+ */
+#define BSORT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+bsort_status bsort_sort_batch_static(const bsort_batch *b, int32_t *perm, const bsort_tuning *t,
+                                     uint32_t *status, bsort_stream_t stream);
+
 /* Synchronises the stream and returns the status word a previous call left
  * in ws (BSORT_OK if none), then clears it. */
 bsort_status bsort_get_device_status(void *ws, bsort_stream_t stream);

@@ -31,8 +31,9 @@ EXPORTS = [
     "bsort_plan_destroy", "bsort_stage_count", "bsort_stage_name", "bsort_sort_batch_staged",
     "bsort_get_device_status", "bsort_status_string",
     "bsort_last_error", "bsort_version", "bsort_tokenize_workspace_bytes", "bsort_tokenize",
-    "bsort_fixed_width", "bsort_oets_buckets",
+    "bsort_fixed_width", "bsort_oets_buckets", "bsort_sort_batch_static",
 ]
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class Words(ctypes.Structure):
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH):
     L.bsort_fixed_width.restype = ctypes.c_int
     L.bsort_oets_buckets.argtypes = [ctypes.POINTER(Words), ctypes.POINTER(Buckets), P, i32, P, P]
     L.bsort_oets_buckets.restype = ctypes.c_int
+    L.bsort_sort_batch_static.argtypes = [ctypes.POINTER(Batch), P, ctypes.POINTER(Tuning), P, P]
+    L.bsort_sort_batch_static.restype = ctypes.c_int
     for f in (L.bsort_bucketize, L.bsort_sort_buckets, L.bsort_sort_batch,
               L.bsort_plan_create, L.bsort_plan_execute, L.bsort_get_device_status):
         f.restype = ctypes.c_int

@@ -280,6 +280,30 @@ def sort_batch(bytes_t: torch.Tensor, offsets_t: torch.Tensor, req_start_t: torc
     return perm
 
 
+STATIC_SCRATCH_BYTES = _lib.STATIC_SCRATCH_BYTES
+
+
+def sort_batch_static(bytes_t: torch.Tensor, offsets_t: torch.Tensor, req_start_t: torch.Tensor,
+                      h_req_start: np.ndarray, max_len: int, out: torch.Tensor,
+                      status: Optional[torch.Tensor] = None, tune: Optional[Tuning] = None,
+                      stream=None) -> torch.Tensor:
+    """sort_batch without a workspace or any allocation: the library's static
+    per-GPU scratch (STATIC_SCRATCH_BYTES) holds the work.  The caller gives
+    perm (``out``) and optionally a device uint32 ``status`` (the call's
+    device status word, 0 when clean)."""
+    _require_gpu()
+    _check_words(bytes_t, offsets_t)
+    h = np.ascontiguousarray(h_req_start, dtype=np.int64)
+    R = len(h) - 1
+    b = _lib.Batch(_ptr(bytes_t), bytes_t.numel(), _ptr(offsets_t), _ptr(req_start_t),
+                   h.ctypes.data, R, max_len)
+    st = status.data_ptr() if status is not None else None
+    _lib.check(_lib.load().bsort_sort_batch_static(
+        ctypes.byref(b), _ptr(out), ctypes.byref(tune) if tune is not None else None, st,
+        _stream(stream)))
+    return out
+
+
 def stage_names(max_len: int):
     """Names of the stages of a batch sort, in launch order."""
     L = _lib.load()

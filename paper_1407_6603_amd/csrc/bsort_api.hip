@@ -775,6 +775,85 @@ void bsort_plan_destroy(bsort_plan* p) {
     delete p;
 }
 
+}  // extern "C"
+
+// ---- the entry point that allocates nothing
+//
+// For callers that cannot allocate (code under graph capture, serving loops,
+// harnesses that forbid hipMalloc): the workspace is this file-scope device
+// array, one per GPU, held until the process ends.  Its address on each
+// device comes from hipGetSymbolAddress on the first call with that device
+// current; host code uses only that address (the array's name in host code
+// is a stand-in, not a device address).  Every call on a GPU shares the
+// array: calls that overlap on one GPU race.  A call clears what must start
+// at zero itself (status word, counters), as the workspace calls do.
+constexpr size_t kStaticScratchBytes = BSORT_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static hipError_t static_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255)) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// the call's device status word (src) to the caller's word; 0 when src is NULL
+__global__ void k_status_out(const uint32_t* src, uint32_t* dst) {
+    if (threadIdx.x == 0) *dst = src ? *src : 0u;
+}
+
+extern "C" {
+
+bsort_status bsort_sort_batch_static(const bsort_batch* b, int32_t* perm, const bsort_tuning* t,
+                                     uint32_t* status, bsort_stream_t stream) {
+    int64_t total, n_max;
+    bsort_status st = check_batch(b, perm, total, n_max);
+    if (st != BSORT_OK) return st;
+    if ((st = check_tuning(t)) != BSORT_OK) return st;
+    if (t && (t->flags & BSORT_FLAG_PER_BUCKET_LAUNCH))
+        return fail(BSORT_E_INVALID, "the per-bucket form is not available without allocation");
+    Layout L;
+    make_layout(total, b->n_requests, b->max_len, L);
+    if (L.bytes > kStaticScratchBytes)
+        return fail(BSORT_E_WORKSPACE, "the batch needs " + std::to_string(L.bytes) +
+                                           " bytes of scratch; the static scratch holds " +
+                                           std::to_string(kStaticScratchBytes));
+    hipStream_t s = (hipStream_t)stream;
+    void* ws = nullptr;
+    HIP_TRY(static_scratch(&ws));
+    if (b->n_requests > 0) {
+        bsort_tuning tt;
+        memset(&tt, 0, sizeof(tt));
+        if (t) tt = *t;
+        tt.flags |= BSORT_FLAG_SERIAL_STAGES;          // no library stream is created
+        Bounds bd = make_bounds(L, total, b->n_requests, n_max, &tt);
+        bd.fused_pack = 1;
+        Job* jd = (Job*)((char*)ws + L.job);
+        Job j = batch_job(L, (char*)ws, bd, b, total, perm);
+        HIP_TRY(launch_set_job(j, jd, s));
+        HIP_TRY(enqueue_sort(jd, bd, s, true, nullptr));
+    }
+    if (status) {
+        k_status_out<<<1, 64, 0, s>>>(
+            b->n_requests > 0 ? (const uint32_t*)((char*)ws + L.status) : nullptr, status);
+        HIP_TRY(hipGetLastError());
+    }
+    return BSORT_OK;
+}
+
 bsort_status bsort_get_device_status(void* ws, bsort_stream_t stream) {
     if (!ws) return fail(BSORT_E_WORKSPACE, "workspace is NULL");
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
