@@ -434,6 +434,62 @@ __device__ __forceinline__ void sort_tile_full1_k(const Src& src, int n, int lan
     }
 }
 
+// Records of 3-byte words (key dword b0 b1 b2 0, index) in one dword when
+// every first byte of the tile is below 0x80: the key's 23 significant bits
+// above the record's position in the tile (9 bits: tiles of at most 512
+// records), compared whole by v_min_u32/v_max_u32 like the one-dword records
+// above, half the issue cost of the two-dword fp64 form.  Positions follow
+// input order, so this is the (key, index) order.  The sorted dwords give
+// back each key and, through the index plane at the position each carries,
+// each index: the wave reads all of them before it writes any.  Padding is
+// all ones; with n < 512 no record reaches it, with n = 512 there is none.
+// A tile with a first byte >= 0x80 takes the two-dword phases.
+template <int K>
+__device__ __forceinline__ void sort_tile_pack3(const LdsTile& src, int n, int lane) {
+    static_assert(K * kWave <= 512, "tile positions take 9 bits");
+    uint32_t r[K][2];
+    src.template load<2, K>(r, lane);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (lane * K + k < n && r[k][0] >= 0x80000000u) ok = false;
+    if (__all(ok)) {
+        uint32_t x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int j = lane * K + k;
+            x[k] = j < n ? ((r[k][0] >> 8) << 9) | (uint32_t)j : 0xFFFFFFFFu;
+        }
+        phases_u32<K>(x, n);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (lane * K + k < n) {                    // (the store keeps these only)
+                r[k][0] = (x[k] >> 9) << 8;
+                r[k][1] = src.lds[src.cap + lsw(src.t0 + (int)(x[k] & 511u))];
+            }
+        }
+    } else {
+        bool f64 = true;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (lane * K + k < n && r[k][0] >= kF64KeyLimit) f64 = false;
+        if (__all(f64)) phases_f64<K>(r, n);
+        else phases_int<2, K>(r, n);
+    }
+    src.template store<2, K>(r, lane);
+}
+
+template <int K, int KCAP>
+__device__ __forceinline__ void sort_tile_pack3_k(const LdsTile& src, int n, int lane,
+                                                  int kneed) {
+    if constexpr (K * 2 > KCAP) {
+        sort_tile_pack3<K>(src, n, lane);
+    } else {
+        if (kneed <= K) sort_tile_pack3<K>(src, n, lane);
+        else sort_tile_pack3_k<K * 2, KCAP>(src, n, lane, kneed);
+    }
+}
+
 template <int K, int KCAP, class Src>
 __device__ __forceinline__ void sort_tile_full2_k(const Src& src, int n, int lane, int kneed) {
     if constexpr (K * 2 > KCAP) {
@@ -845,6 +901,10 @@ __device__ __forceinline__ void lds_sort_entry(const Job* __restrict__ J, const 
         if constexpr (D == 2) {
             if (full1) {
                 sort_tile_full1_k<2, KCAP>(src, tn, lane, (tn + kWave - 1) / kWave);
+                continue;
+            }
+            if (bk.L == 3) {
+                sort_tile_pack3_k<2, KCAP>(src, tn, lane, (tn + kWave - 1) / kWave);
                 continue;
             }
         }

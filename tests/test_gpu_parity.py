@@ -359,6 +359,47 @@ def test_one_two_byte_words_in_every_class(bs, ws, alphabet):
         assert np.array_equal(got, expect), T
 
 
+@pytest.mark.parametrize("alphabet", [b"eatonsEAT", None, b"\x00\x01\x7f\x80\xfe\xff",
+                                      "sprinkle", "max_packed"])
+def test_three_four_byte_words_in_every_class(bs, ws, alphabet):
+    """3- and 4-byte words (two-dword records; in LDS a tile of 3-byte words
+    whose first bytes are all below 0x80 sorts as one dword per record, the
+    key's bits above the tile position): letters, all byte values and the
+    extreme bytes (tiles with a first byte >= 0x80 take the two-dword form),
+    letters with a sprinkle of high first bytes (some tiles packed, some
+    not), and keys at the packed form's top (7F FF FE/FF, full tiles
+    included), heavy duplicates, sizes at every two-dword size class and
+    past the largest (merged through HBM)."""
+    rng = np.random.default_rng(34)
+    lists = []
+    for cap in lds_caps(2) + [16384 + 129]:
+        for L in (3, 4):
+            for n in (cap - 1, cap // 2 + 3, 1024):
+                if alphabet is None:
+                    w = wordgen.random_words(rng, n, L, L)
+                elif alphabet == "sprinkle":
+                    pool = wordgen.random_words(rng, 40, L, L, alphabet=b"eatonsEAT").as_list()
+                    words = [pool[i] for i in rng.integers(0, 40, n)]
+                    for i in rng.integers(0, n, max(1, n // 700)):
+                        words[i] = bytes([0x80 + int(rng.integers(0, 128))]) + words[i][1:]
+                    w = wordgen.Words.from_list(words)
+                elif alphabet == "max_packed":
+                    head = b"\x7f" + b"\xff" * (L - 2)
+                    w = wordgen.Words.from_list(
+                        [head + bytes([int(x)]) for x in rng.choice([0xFE, 0xFF], n)])
+                else:
+                    pool = wordgen.random_words(rng, 40, L, L, alphabet=alphabet).as_list()
+                    w = wordgen.Words.from_list([pool[i] for i in rng.integers(0, 40, n)])
+                lists.append(w)
+    batch = wordgen.Batch.concat(lists)
+    expect = oracle.definition_sort_batch(batch.bytes, batch.offsets, batch.req_start, 16)
+    for T in (128, 512):
+        got = gpu_batch(bs, ws, batch, 4, tune=bs.tuning(T, 0))
+        assert np.array_equal(got, expect), T
+        got = gpu_batch(bs, ws, batch, 4, tune=bs.tuning(T, 0, bs.FLAG_LDS_TILE))
+        assert np.array_equal(got, expect), (T, "tuned in-LDS tile")
+
+
 @pytest.mark.parametrize("alphabet", [b"eatonsEAT", None, b"\x00\x01\x7f\x80\xfe\xff"])
 def test_nine_ten_byte_words_in_every_class(bs, ws, alphabet):
     """9- and 10-byte words (four-dword records, the last key dword half
