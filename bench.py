@@ -33,11 +33,30 @@ if ROOT not in sys.path:
 
 import wordgen  # noqa: E402
 
-# 32-bit VALU peak from the fp32 vector figure (157.3 TFLOP/s = 78.6 T FMA
-# lanes/s): 256 CUs x 128 lanes/clk x 2.4 GHz
-PEAK_INT32_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Peaks derived from the chip's unit counts and clock (256 CUs, 4 SIMDs of 16
+# lanes each, 2.4 GHz).  A VALU instruction (32-bit, or a 64-bit min/max)
+# issues one wave of 64 lanes per SIMD every 4 clocks: 64 lanes/clk/CU, 39.3 T
+# lane-instructions/s (the fp64 vector FMA figure, 78.6 TFLOP/s, is that rate
+# at 2 flops per FMA).  LDS: 128 B/clk/CU written and 256 B/clk/CU read
+# (CDNA4 doubled the read path).  The probes in libbsort_probe measure each.
+CLK_HZ = 2.4e9
+VALU_TIPS = 256 * 64 * CLK_HZ / 1e12                # 39.3 T lane-instructions/s
 PEAK_HBM_GBS = 8000.0
-PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12       # 128 B/clk/CU LDS bandwidth: 78.6 TB/s
+PEAK_LDS_READ_TBS = 256 * 256 * CLK_HZ / 1e12       # 157.3 TB/s
+PEAK_LDS_WRITE_TBS = 256 * 128 * CLK_HZ / 1e12      # 78.6 TB/s
+
+
+def ce_cost(D, L, in_lds):
+    """VALU instructions per lane for one compare-exchange of records of D
+    dwords (words of L bytes) in the form the library uses: a min and a max
+    (v_min_u32/v_max_u32 on one-dword records of 1- and 2-byte words and
+    3-byte words in LDS, v_min_f64/v_max_f64 on two-dword records and the
+    two-dword form of 5- and 6-byte words in LDS): 2; otherwise a compare per
+    key dword and two selects per dword: 3D - 1 (an estimate of the
+    compiler's form)."""
+    if D == 2 or (in_lds and D == 3 and L <= 6):
+        return 2.0
+    return 3.0 * D - 1.0
 
 
 # HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE counter runs in
@@ -164,8 +183,10 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys, ld
         n = n[n >= 2]
         single = n[n <= T]
         hbm = n[(n > max(T, cap))]
-        t = out.setdefault(f"tiles_d{D}", {"ce": 0, "words": 0, "D": D})
-        t["ce"] += int(tile_ce(single, T).sum()) + int(tile_ce(hbm, Th).sum())
+        t = out.setdefault(f"tiles_d{D}", {"ce": 0, "words": 0, "D": D, "slots": 0.0})
+        tce = int(tile_ce(single, T).sum()) + int(tile_ce(hbm, Th).sum())
+        t["ce"] += tce
+        t["slots"] += tce * ce_cost(D, L, False)
         t["words"] += int(single.sum()) + int(hbm.sum())
         lo = T
         for c in caps:
@@ -175,9 +196,11 @@ def workload_structure(offsets, req_start, max_len, tile_keys, hbm_tile_keys, ld
                 continue
             Tc = lds_tile(T, c, D, lds_fixed)
             l = out.setdefault(f"lds_d{D}_{c}", {"ce": 0, "words": 0, "D": D, "lds_bytes": 0,
-                                                 "buckets": 0, "tile": Tc})
+                                                 "buckets": 0, "tile": Tc, "slots": 0.0})
             l["buckets"] += int(len(lds))
-            l["ce"] += int(tile_ce(lds, Tc).sum())
+            lce = int(tile_ce(lds, Tc).sum())
+            l["ce"] += lce
+            l["slots"] += lce * ce_cost(D, L, True)
             l["words"] += int(lds.sum())
             p = (lds + Tc - 1) // Tc
             # each phase reads and writes the paired part of the sub-array in LDS
@@ -459,6 +482,7 @@ def main():
                     help="hbm_tile_keys, the merge-split block width through HBM "
                          "(0: autotune cache or library default)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-bucket launch form")
+    ap.add_argument("--no-probes", action="store_true", help="skip the roofline probes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -531,6 +555,11 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # measured ceilings (libbsort_probe.so) beside the derived ones
+    peaks = None
+    if not args.no_probes:
+        from paper_1407_6603_amd import probe
+        peaks = probe.peaks(reps=2)
 
     tile, hbm_tile, tflags, tuned_from = args.tile, args.hbm_tile, args.tune_flags, "flags"
     if tile == 0 and hbm_tile == 0:
@@ -613,6 +642,23 @@ def main():
     worked = [k for k in stage_ms if k in struct or (k == "merge_split" and merge_bytes)]
     alone = serial["stage_ms"] if serial else stage_ms
     dom = max(worked, key=lambda k: alone.get(k, 0.0))
+
+    # ---- the dominant in-LDS stage with its merge phases skipped (tiles
+    # only, every stage alone in order; its tile size as in the full sort)
+    tiles_only_ms = None
+    if not args.no_serial and dom in struct and dom.startswith("lds_"):
+        ttune = bs.tuning(struct[dom]["tile"], 0,
+                          bs.FLAG_SERIAL_STAGES | bs.FLAG_TILES_ONLY | tflags, hbm_tile)
+        tperm = torch.empty(total, dtype=torch.int32, device=dev)
+        reps = min(max(args.steps, 1), 5)
+        ttimers = [bs.StageTimer(max_len, stream, only={dom}) for _ in range(reps + 1)]
+        for t in ttimers:
+            bs.sort_batch_staged(b_t, o_t, rs_t, batch.req_start, max_len, t, ttune, ws,
+                                 out=tperm)
+        torch.cuda.synchronize()
+        bs.check_device_status(ws)
+        tiles_only_ms = sum(t.ms()[dom] for t in ttimers[1:]) / reps
+        del tperm
 
     # ---- timed region: K steps back to back on one stream, HIP events
     # around the dominant stage's launch only (read after the region)
@@ -822,27 +868,57 @@ def main():
     if dom in struct:
         w = struct[dom]
         D, ce, sec = w["D"], w["ce"], dom_ms / 1e3
-        ops = 3 * D * ce                       # D dword compares + 2D dword selects per CE
-        achieved = ops / sec / 1e12
+        # the tile sorts' compare-exchanges at their VALU cost (ce_cost), over
+        # the whole launch (tile sorts and merge phases)
+        achieved = w["slots"] / sec / 1e12
         roof = {"bound": "alu", "kernel": kernel_name(dom), "achieved": achieved,
-                "peak": PEAK_INT32_TOPS, "unit": "TOP/s", "frac": achieved / PEAK_INT32_TOPS,
+                "peak": VALU_TIPS, "unit": "T lane-instructions/s",
+                "frac": achieved / VALU_TIPS,
+                "work": "tile compare-exchanges x VALU instructions each (min + max: 2)",
                 "traffic": measured_traffic(kernel_name(dom)),
                 # key lanes (8 B each) read, perm read and written (4 + 4 B) per word
                 "hbm_bytes_algorithmic": (8 * (D // 2) + 8) * w["words"],
                 "launch_ms": dom_ms, "launch_ms_alone": alone.get(dom),
-                "ce_per_launch": ce,
-                "ce_per_s": ce / sec, "ops_per_ce": 3 * D, "words_per_launch": w["words"]}
+                "ce_per_launch": ce, "ce_per_s": ce / sec,
+                "valu_lane_instructions_per_launch": w["slots"], "words_per_launch": w["words"]}
+        if peaks:
+            m = peaks["f64_minmax"]["rate"] / 1e12
+            roof["peak_measured"] = m
+            roof["peak_measured_probe"] = "f64_minmax"
+            roof["frac_measured"] = achieved / m
+        if tiles_only_ms:
+            # the same launch with the merge phases skipped: the tile sorts'
+            # own rate, and the share of the launch the merge phases take
+            roof["tiles_only_ms"] = tiles_only_ms
+            roof["tiles_only_frac"] = w["slots"] / (tiles_only_ms / 1e3) / 1e12 / VALU_TIPS
+            if alone.get(dom):
+                roof["merge_share_alone"] = 1.0 - tiles_only_ms / alone[dom]
         if "lds_bytes" in w:
+            # the tile step at its issue floor plus the merge phases' LDS bytes
+            # (half read, half written) at the LDS peaks
             roof["merge_lds_bytes"] = w["lds_bytes"]
-            roof["floor_ms"] = (ops / (PEAK_INT32_TOPS * 1e12)
-                                + w["lds_bytes"] / (PEAK_LDS_TBS * 1e12)) * 1e3
+            roof["floor_ms"] = (w["slots"] / (VALU_TIPS * 1e12)
+                                + w["lds_bytes"] / 2 / (PEAK_LDS_READ_TBS * 1e12)
+                                + w["lds_bytes"] / 2 / (PEAK_LDS_WRITE_TBS * 1e12)) * 1e3
+            roof["frac_of_floor"] = roof["floor_ms"] / dom_ms
+            # the roofline the paper's compare-exchange count suggests if every
+            # compare-exchange read and wrote its records in LDS: 2 reads and 2
+            # writes of (8W + 4) bytes (W = 1 key lane here).  The tiles keep
+            # records in registers, so it does not bind: frac > 1
+            ce_rd = ce * 2 * 12
+            lds_ce_ms = (ce_rd / (PEAK_LDS_READ_TBS * 1e12)
+                         + ce_rd / (PEAK_LDS_WRITE_TBS * 1e12)) * 1e3
+            roof["lds_compare_exchange"] = {
+                "bytes": 2 * ce_rd, "floor_ms": lds_ce_ms, "frac": lds_ce_ms / dom_ms,
+                "peaks_tb_s": {"read": PEAK_LDS_READ_TBS, "write": PEAK_LDS_WRITE_TBS}}
         # all in-LDS classes together, over the span from the first class's
         # start to the last one's end (they run concurrently)
-        lds_ce = sum(w["ce"] * 3 * w["D"] for k, w in struct.items() if k.startswith("lds_"))
+        lds_slots = sum(w["slots"] for k, w in struct.items() if k.startswith("lds_"))
         roof["lds_all_classes"] = {
-            "span_ms": lds_span, "ops": lds_ce,
-            "achieved": lds_ce / (lds_span / 1e3) / 1e12, "peak": PEAK_INT32_TOPS,
-            "unit": "TOP/s", "frac": lds_ce / (lds_span / 1e3) / 1e12 / PEAK_INT32_TOPS}
+            "span_ms": lds_span, "valu_lane_instructions": lds_slots,
+            "achieved": lds_slots / (lds_span / 1e3) / 1e12, "peak": VALU_TIPS,
+            "unit": "T lane-instructions/s",
+            "frac": lds_slots / (lds_span / 1e3) / 1e12 / VALU_TIPS}
     elif dom == "merge_split" and merge_bytes:
         achieved = merge_bytes / (dom_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": "k_merge_sched", "achieved": achieved,
@@ -886,6 +962,10 @@ def main():
                    "lds_tile": "tuned" if tflags & autotune.FLAG_LDS_TILE else "library",
                    "tuning_source": tuned_from, "parallelism": "single GPU"},
         "graph_plan": graph,
+        "measured_peaks": peaks,
+        "derived_peaks": {"valu_t_lane_instr_per_s": VALU_TIPS,
+                          "lds_read_tb_s": PEAK_LDS_READ_TBS,
+                          "lds_write_tb_s": PEAK_LDS_WRITE_TBS, "hbm_gb_s": PEAK_HBM_GBS},
         "per_bucket_launch": plain,
         "batched_over_per_bucket": (value / plain["value"]) if plain else None,
         "stage_ms": stage_ms,

@@ -22,21 +22,27 @@
 extern "C" {
 #endif
 
-#define BSORT_PROBE_F64_MINMAX 0      /* v_min_f64 + v_max_f64 per step; unit: lane instructions */
-#define BSORT_PROBE_U32_MINMAX 1      /* v_min_u32 + v_max_u32; unit: lane instructions */
+#define BSORT_PROBE_F64_MINMAX 0      /* v_min_f64, v_max_f64; unit: lane instructions */
+#define BSORT_PROBE_U32_MINMAX 1      /* v_min_u32, v_max_u32; unit: lane instructions */
 #define BSORT_PROBE_U64_CMP_SELECT 2  /* 64-bit compare and four dword selects (as the compiler
                                          forms them); unit: compare-exchanges per lane */
-#define BSORT_PROBE_DPP_MOVE 3        /* v_add_u32 + a DPP row move; unit: lane instructions */
-#define BSORT_PROBE_U32_ADD 4         /* two dependent v_add_u32; unit: lane instructions */
+#define BSORT_PROBE_DPP_MOVE 3        /* v_mov_b32 DPP row moves; unit: lane instructions */
+#define BSORT_PROBE_U32_ADD 4         /* v_add_u32; unit: lane instructions */
 #define BSORT_PROBE_LDS_READ 5        /* 16-byte LDS reads, no bank conflicts; unit: bytes */
 #define BSORT_PROBE_LDS_WRITE 6       /* 16-byte LDS writes, no bank conflicts; unit: bytes */
 #define BSORT_PROBE_HBM_READ 7        /* 16-byte global loads streaming HBM; unit: bytes */
 #define BSORT_PROBE_HBM_COPY 8        /* read + write streams; unit: bytes read plus written */
 
 /*
+ * The ALU probes issue, per loop trip and lane, 32 instructions of their
+ * kind in two rounds of 16 independent chains (an instruction depends on its
+ * chain's instruction 16 earlier), so the rate is the issue ceiling, not a
+ * latency; the LDS probes make four 16-byte accesses per trip at immediate
+ * offsets with two VALU instructions per read.
+ *
  * Runs probe `probe` on the current device, on `stream` (a hipStream_t as
- * void*), and waits for it.  iters: loop trips per lane (ALU and LDS probes,
- * each trip 8 independent chains) or passes over the buffer (HBM probes).
+ * void*), and waits for it.  iters: loop trips per lane (ALU and LDS probes)
+ * or passes over the buffer (HBM probes).
  * scratch: caller-owned device memory of scratch_bytes >= 64 MiB (the HBM
  * probes stream its part past the first 32 MiB, as two halves).  Writes the
  * probe's device time in milliseconds (HIP events around the launches) to

@@ -13,73 +13,81 @@
 namespace {
 
 constexpr int kThreads = 1024;          // 16 waves per workgroup
-constexpr int kChains = 8;              // independent chains per lane
+constexpr int kChains = 16;             // independent chains per lane
 
 // a DPP row move, lane i reading lane i+1 (the library's odd-phase exchange)
 constexpr int kDppWaveShl1 = 0x130;
 
+// Every ALU probe issues 2*kChains instructions per loop trip, in two rounds
+// of kChains independent instructions; an instruction of the second round
+// reads the result of the first round's instruction of its chain, kChains
+// instructions earlier, so no instruction waits on the one just before it.
+// The instructions are written in inline asm, each as the only instruction
+// of its statement, so the loop issues exactly these (plus the loop's own
+// scalar counter); the operands are registers that stay live.
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_valu(int64_t iters, uint32_t* sink) {
     const uint32_t t = threadIdx.x + blockIdx.x * kThreads;
     if constexpr (KIND == BSORT_PROBE_F64_MINMAX) {
-        double a[kChains], b[kChains];
+        double x[kChains], y[kChains];
 #pragma unroll
         for (int c = 0; c < kChains; ++c) {
-            a[c] = (double)(t + c);
-            b[c] = (double)(t ^ (c * 977));
+            x[c] = 1.0 + (double)(t & 1023) + c;        // positive normal doubles
+            y[c] = 2.0 + (double)((t * 7u) & 1023);
         }
         for (int64_t i = 0; i < iters; ++i) {
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) {
-                double lo, hi;
-                asm volatile("v_min_f64 %0, %2, %3\n\tv_max_f64 %1, %2, %3"
-                             : "=&v"(lo), "=&v"(hi) : "v"(a[c]), "v"(b[c]));
-                a[c] = hi;
-                b[c] = lo;
-            }
+            for (int c = 0; c < kChains; ++c)
+                asm volatile("v_min_f64 %0, %0, %1" : "+v"(x[c]) : "v"(y[c]));
+#pragma unroll
+            for (int c = 0; c < kChains; ++c)
+                asm volatile("v_max_f64 %0, %0, %1" : "+v"(y[c]) : "v"(x[c]));
         }
         double s = 0;
 #pragma unroll
-        for (int c = 0; c < kChains; ++c) s += a[c] - b[c];
-        if (s == -1.0) sink[t] = 1u;
+        for (int c = 0; c < kChains; ++c) s += x[c] - y[c];
+        if (s == 1.0) sink[t] = 1u;
     } else if constexpr (KIND == BSORT_PROBE_U32_MINMAX || KIND == BSORT_PROBE_U32_ADD) {
-        uint32_t a[kChains], b[kChains];
+        uint32_t x[kChains], y[kChains];
 #pragma unroll
         for (int c = 0; c < kChains; ++c) {
-            a[c] = t * 2654435761u + c;
-            b[c] = t ^ (c * 977u);
+            x[c] = t * 2654435761u + c;
+            y[c] = t ^ (c * 977u);
         }
         for (int64_t i = 0; i < iters; ++i) {
+            if constexpr (KIND == BSORT_PROBE_U32_MINMAX) {
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) {
-                uint32_t lo, hi;
-                if constexpr (KIND == BSORT_PROBE_U32_MINMAX)
-                    asm volatile("v_min_u32 %0, %2, %3\n\tv_max_u32 %1, %2, %3"
-                                 : "=&v"(lo), "=&v"(hi) : "v"(a[c]), "v"(b[c]));
-                else
-                    asm volatile("v_add_u32 %0, %2, %3\n\tv_add_u32 %1, %2, %0"
-                                 : "=&v"(lo), "=&v"(hi) : "v"(a[c]), "v"(b[c]));
-                a[c] = hi;
-                b[c] = lo;
+                for (int c = 0; c < kChains; ++c)
+                    asm volatile("v_min_u32 %0, %0, %1" : "+v"(x[c]) : "v"(y[c]));
+#pragma unroll
+                for (int c = 0; c < kChains; ++c)
+                    asm volatile("v_max_u32 %0, %0, %1" : "+v"(y[c]) : "v"(x[c]));
+            } else {
+#pragma unroll
+                for (int c = 0; c < kChains; ++c)
+                    asm volatile("v_add_u32 %0, %0, %1" : "+v"(x[c]) : "v"(y[c]));
+#pragma unroll
+                for (int c = 0; c < kChains; ++c)
+                    asm volatile("v_add_u32 %0, %0, %1" : "+v"(y[c]) : "v"(x[c]));
             }
         }
         uint32_t s = 0;
 #pragma unroll
-        for (int c = 0; c < kChains; ++c) s ^= a[c] ^ b[c];
+        for (int c = 0; c < kChains; ++c) s ^= x[c] ^ y[c];
         if (s == 0x9E3779B9u) sink[t] = s;
     } else if constexpr (KIND == BSORT_PROBE_U64_CMP_SELECT) {
         // compare two 64-bit keys and select both 32-bit halves of both records
-        uint64_t a[kChains], b[kChains];
+        // (the compiler's own form of the library's integer compare-exchange)
+        uint64_t a[kChains / 2], b[kChains / 2];
 #pragma unroll
-        for (int c = 0; c < kChains; ++c) {
+        for (int c = 0; c < kChains / 2; ++c) {
             a[c] = ((uint64_t)t << 32) | (t * 2654435761u + c);
             b[c] = ((uint64_t)(t ^ c) << 32) | (t * 40503u);
         }
         for (int64_t i = 0; i < iters; ++i) {
-            uint64_t lo[kChains], hi[kChains];
+            uint64_t lo[kChains / 2], hi[kChains / 2];
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) {
-                // the library's integer compare-exchange: one 64-bit compare, four selects
+            for (int c = 0; c < kChains / 2; ++c) {
                 const bool g = a[c] > b[c];
                 lo[c] = g ? b[c] : a[c];
                 hi[c] = g ? a[c] : b[c];
@@ -87,35 +95,46 @@ __global__ __launch_bounds__(kThreads) void k_valu(int64_t iters, uint32_t* sink
             // the next step pairs one chain's larger record with the next chain's
             // smaller one, so no order between them is known in advance
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) {
+            for (int c = 0; c < kChains / 2; ++c) {
                 a[c] = hi[c];
-                b[c] = lo[(c + 1) % kChains];
+                b[c] = lo[(c + 1) % (kChains / 2)];
             }
         }
         uint64_t s = 0;
 #pragma unroll
-        for (int c = 0; c < kChains; ++c) s ^= a[c] ^ b[c];
+        for (int c = 0; c < kChains / 2; ++c) s ^= a[c] ^ b[c];
         if (s == 0x9E3779B97F4A7C15ull) sink[t] = 1u;
     } else if constexpr (KIND == BSORT_PROBE_DPP_MOVE) {
-        int a[kChains];
+        // row moves alone: x <- y of the next lane, then y <- x of the next lane
+        int x[kChains], y[kChains];
 #pragma unroll
-        for (int c = 0; c < kChains; ++c) a[c] = (int)(t + c);
+        for (int c = 0; c < kChains; ++c) {
+            x[c] = (int)(t + c);
+            y[c] = (int)(t ^ c);
+        }
         for (int64_t i = 0; i < iters; ++i) {
 #pragma unroll
             for (int c = 0; c < kChains; ++c)
-                a[c] = __builtin_amdgcn_update_dpp(a[c], a[c] + c, kDppWaveShl1, 0xF, 0xF,
-                                                   false);
+                x[c] = __builtin_amdgcn_update_dpp(x[c], y[c], kDppWaveShl1, 0xF, 0xF, false);
+#pragma unroll
+            for (int c = 0; c < kChains; ++c)
+                y[c] = __builtin_amdgcn_update_dpp(y[c], x[c], kDppWaveShl1, 0xF, 0xF, false);
         }
         int s = 0;
 #pragma unroll
-        for (int c = 0; c < kChains; ++c) s ^= a[c];
+        for (int c = 0; c < kChains; ++c) s ^= x[c] ^ y[c];
         if (s == 0x12345678) sink[t] = 1u;
     }
 }
 
 // LDS: each lane moves 16 bytes per access, consecutive lanes consecutive
-// 16-byte words (no bank conflicts); 64 KiB per workgroup.
+// 16-byte words (no bank conflicts); 64 KiB per workgroup.  A loop trip makes
+// four accesses at immediate offsets 16 KiB apart from one base address,
+// which changes once per trip; a read's four dwords are folded into two
+// running three-input XORs (two VALU instructions per 1 KiB a wave reads);
+// a write stores one register quad.
 constexpr int kLdsWords = 64 * 1024 / 16;
+constexpr int kXor3 = 0x96;             // v_bitop3_b32 truth table of a ^ b ^ c
 
 template <bool WRITE>
 __global__ __launch_bounds__(kThreads) void k_lds(int64_t iters, uint32_t* sink) {
@@ -123,25 +142,30 @@ __global__ __launch_bounds__(kThreads) void k_lds(int64_t iters, uint32_t* sink)
     const int tid = threadIdx.x;
     for (int i = tid; i < kLdsWords; i += kThreads) buf[i] = make_uint4(i, i + 1, i + 2, i + 3);
     __syncthreads();
-    uint4 acc = make_uint4(0, 0, 0, 0);
+    uint32_t a0 = 0, a1 = 0;
+    const uint4 w = make_uint4(tid, tid + 1, tid * 3, 7);
     for (int64_t it = 0; it < iters; ++it) {
+        // tid XOR a value below 64 permutes each group of 64 lanes: still
+        // consecutive 16-byte words per group of 16 lanes
+        const int b = tid ^ ((int)it & 63);
 #pragma unroll
         for (int r = 0; r < kLdsWords / kThreads; ++r) {
-            const int i = (tid + r * kThreads + (int)it * 64) & (kLdsWords - 1);
             if constexpr (WRITE) {
-                buf[i] = make_uint4((uint32_t)it, r, tid, 7);
+                buf[b + r * kThreads] = w;
             } else {
-                const uint4 v = buf[i];
-                acc.x ^= v.x;
-                acc.y += v.y;
-                acc.z ^= v.z;
-                acc.w += v.w;
+                const uint4 v = buf[b + r * kThreads];
+                a0 = __builtin_amdgcn_bitop3_b32(a0, v.x, v.y, kXor3);
+                a1 = __builtin_amdgcn_bitop3_b32(a1, v.z, v.w, kXor3);
             }
         }
-        if constexpr (WRITE) __syncthreads();
     }
-    if constexpr (WRITE) acc = buf[(tid * 7) & (kLdsWords - 1)];
-    if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x5A5A5A5Au) sink[blockIdx.x * kThreads + tid] = 1u;
+    if constexpr (WRITE) {
+        __syncthreads();
+        const uint4 v = buf[(tid * 7) & (kLdsWords - 1)];
+        a0 = v.x ^ v.y;
+        a1 = v.z ^ v.w;
+    }
+    if ((a0 ^ a1) == 0x5A5A5A5Au) sink[blockIdx.x * kThreads + tid] = 1u;
 }
 
 // HBM: every lane streams 16-byte words, grid-stride (read, or read + write)
@@ -209,11 +233,11 @@ int bsort_probe_run(int probe, int64_t iters, void* scratch, size_t scratch_byte
             break;
         case BSORT_PROBE_U64_CMP_SELECT:
             k_valu<BSORT_PROBE_U64_CMP_SELECT><<<grid, kThreads, 0, s>>>(iters, sink);
-            *units = lanes * iters * kChains;          // compare-exchanges
+            *units = lanes * iters * (kChains / 2);    // compare-exchanges
             break;
         case BSORT_PROBE_DPP_MOVE:
             k_valu<BSORT_PROBE_DPP_MOVE><<<grid, kThreads, 0, s>>>(iters, sink);
-            *units = lanes * iters * kChains * 2;      // the add and the row move
+            *units = lanes * iters * kChains * 2;      // row moves
             break;
         case BSORT_PROBE_LDS_READ:
             k_lds<false><<<grid, kThreads, 0, s>>>(iters, sink);

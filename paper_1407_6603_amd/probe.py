@@ -25,7 +25,7 @@ PROBES = [
     ("u32_minmax", U32_MINMAX, 4000, "lane instructions/s (v_min_u32, v_max_u32)"),
     ("u32_add", U32_ADD, 4000, "lane instructions/s (v_add_u32)"),
     ("u64_cmp_select", U64_CMP_SELECT, 4000, "compare-exchanges/s (64-bit compares, 4 selects)"),
-    ("dpp_move", DPP_MOVE, 4000, "lane instructions/s (v_add_u32 + v_mov_b32 row move)"),
+    ("dpp_move", DPP_MOVE, 4000, "lane instructions/s (v_mov_b32 row moves)"),
     ("lds_read", LDS_READ, 200, "bytes/s (ds_read_b128)"),
     ("lds_write", LDS_WRITE, 200, "bytes/s (ds_write_b128)"),
     ("hbm_read", HBM_READ, 4, "bytes/s (global_load_dwordx4 stream, 2 GiB)"),
@@ -79,5 +79,25 @@ def peaks(reps: int = 3, scratch_bytes: int = (2 << 30) + (32 << 20)):
 
 
 if __name__ == "__main__":
+    import argparse
     import json
-    print(json.dumps(peaks(), indent=1))
+
+    ap = argparse.ArgumentParser(description="roofline probes on the current GPU")
+    ap.add_argument("--only", default="", help="run one probe (by name) --reps times and "
+                    "print each run's rate; default: the best rate of every probe")
+    ap.add_argument("--iters", type=int, default=0, help="iterations (default: the table's)")
+    ap.add_argument("--reps", type=int, default=3)
+    a = ap.parse_args()
+    if not a.only:
+        print(json.dumps(peaks(reps=a.reps), indent=1))
+    else:
+        row = [r for r in PROBES if r[0] == a.only]
+        if not row:
+            raise SystemExit(f"unknown probe {a.only}; one of {[r[0] for r in PROBES]}")
+        name, p, iters, unit = row[0]
+        scratch = torch.zeros((2 << 30) + (32 << 20) if name.startswith("hbm") else 64 << 20,
+                              dtype=torch.uint8, device="cuda")
+        for _ in range(a.reps):
+            ms, units = run(p, a.iters or iters, scratch)
+            print(json.dumps({"probe": name, "ms": ms, "rate": units / (ms * 1e-3),
+                              "unit": unit}), flush=True)
