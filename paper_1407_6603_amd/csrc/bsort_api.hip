@@ -37,7 +37,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Workspace layout: a pure function of (total words, lists, max_len), so the
 // size a caller asks for and the layout a call uses always agree.
 struct Layout {
-    size_t status, job, chunk_begin, chunk_list, chunk_hist, key_off, keys, tiles[kNumD], tile_count,
+    size_t status, job, chunk_begin, chunk_list, chunk_hist, len8, key_off, keys, tiles[kNumD],
+        tile_count,
         msub, msorted, mcounts, tile_ph, pcnt, pfill, active, pe, po, ps, mhead, counts, starts,
         order, jobs, lbuckets, lb_count, hchunks[kLdsMaxD + 1], hc_count, pmax;
     int64_t chunk_cap, tile_cap, msub_cap, lb_cap;
@@ -68,6 +69,7 @@ bool make_layout(int64_t total, int32_t R, int32_t max_len, Layout& L) {
     L.chunk_begin = take(sizeof(int64_t) * ((size_t)R + 1));
     L.chunk_list = take(sizeof(int32_t) * (size_t)L.chunk_cap);
     L.chunk_hist = take(sizeof(int32_t) * (size_t)L.chunk_cap * L.ml1);
+    L.len8 = take((size_t)total);
     L.key_off = take(sizeof(int64_t) * (size_t)R * L.ml1);
     L.keys = take(sizeof(uint64_t) * (size_t)L.wmax * (size_t)total);
     for (int D = 2; D <= L.dmax && D <= kMaxD; ++D)
@@ -172,6 +174,7 @@ Job base_job(const Layout& L, char* ws, const Bounds& b) {
     j.chunk_begin = (int64_t*)(ws + L.chunk_begin);
     j.chunk_list = (int32_t*)(ws + L.chunk_list);
     j.chunk_hist = (int32_t*)(ws + L.chunk_hist);
+    j.len8 = (uint8_t*)(ws + L.len8);
     j.chunk_cap = L.chunk_cap;
     j.key_off = (int64_t*)(ws + L.key_off);
     j.keys = (uint64_t*)(ws + L.keys);
@@ -928,6 +931,7 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
         j.counts = (int32_t*)(ws + L.counts) + (int64_t)r * ml1;
         j.starts = (int32_t*)(ws + L.starts) + (int64_t)r * (ml1 + 1);
         j.order = (int32_t*)(ws + L.order) + h[r];
+        j.len8 = (uint8_t*)(ws + L.len8) + h[r];
         j.perm = perm + h[r];
         j.keys = (uint64_t*)(ws + L.keys) + (int64_t)wmax * h[r];
         j.key_off = (int64_t*)(ws + L.key_off) + (int64_t)r * ml1;

@@ -184,6 +184,7 @@ struct Job {
     int64_t* chunk_begin;        // [R + 1]
     int32_t* chunk_list;         // [chunk_cap] list of each chunk (R > 1)
     int32_t* chunk_hist;         // [chunk_cap * ml1], scanned in place
+    uint8_t* len8;               // [total] each word's length (0xFF: malformed or too long)
     int64_t chunk_cap;
     int64_t* key_off;            // [R * ml1]
     uint64_t* keys;              // [wmax * total]

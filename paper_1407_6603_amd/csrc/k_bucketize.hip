@@ -5,13 +5,16 @@
 //   k_chunk_plan    one workgroup: chunks per list, their running sum (the
 //                   sort side re-runs it: its chunk map must not depend on
 //                   what an earlier call left in the workspace)
-//   k_chunk_hist    one wave per chunk of 1024 words: length histogram
+//   k_chunk_hist    one wave per chunk of kChunk words: length histogram,
+//                   and each word's length as one byte
 //   k_chunk_scan    one wave per (list, length): exclusive scan over chunks
 //   k_bucket_starts one wave per list: starts = exclusive scan of counts
 //   k_scatter       one wave per chunk: stable placement of word indices
 //
-// Every word is read twice (offsets only): HBM bound, ~16 B/word read and
-// 4 B/word written.  A chunk never straddles two lists.
+// The offsets are read once (8 B/word, by the histogram pass); the scatter
+// reads the length bytes and rebuilds each word's offset as the chunk's
+// first offset plus the lengths before it (a word's bytes end where the
+// next word's begin).  HBM bound.  A chunk never straddles two lists.
 #include "bsort_internal.h"
 
 namespace bsort {
@@ -86,6 +89,24 @@ __device__ __forceinline__ int word_len_o(int64_t o0, int64_t o1, int64_t first,
     return (int)(o1 - o0);
 }
 
+// 64-bit value of the next lane (lane 63 keeps `old`)
+__device__ __forceinline__ int64_t from_next_lane64(int64_t old, int64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)old, (int)(uint32_t)v, 0x130, 0xF,
+                                               0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)((uint64_t)old >> 32),
+                                               (int)(uint32_t)((uint64_t)v >> 32), 0x130, 0xF,
+                                               0xF, false);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int64_t lane0_of(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+constexpr int kHistBatch = 16;                      // rounds whose loads are in flight together
+
 __global__ __launch_bounds__(256) void k_chunk_hist(const Job* __restrict__ J) {
     __shared__ int hist[kTileWavesPerBlock][kMaxLen + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -96,30 +117,37 @@ __global__ __launch_bounds__(256) void k_chunk_hist(const Job* __restrict__ J) {
     const int ml1 = J->ml1, max_len = J->max_len;
     const int64_t n_bytes = J->n_bytes;
     const gptr<const int64_t> offs = gp(J->offsets);
+    const gptr<uint8_t> len8 = gp(J->len8);
     const int64_t first = offs[0];
     for (int L = lane; L < ml1; L += kWave) hist[wv][L] = 0;
     __builtin_amdgcn_wave_barrier();
-    // every word length of the chunk first (independent loads in flight together)
-    // loads at in-range indices (a chunk holds at least one word), no branch
-    // around them, so they are all in flight before the first is used
     uint32_t bad = 0;
-    int64_t oa[kChunkRounds], ob[kChunkRounds];
+    const int rounds = (int)((ge - gs + kWave - 1) / kWave);       // uniform
+    for (int i0 = 0; i0 < rounds; i0 += kHistBatch) {
+        // each word's first offset, once: the next word's comes from the next
+        // lane, or for lane 63 from lane 0 of the next round; offsets[ge]
+        // exists (offsets has total + 1 entries), so every load is in range
+        int64_t o[kHistBatch];
 #pragma unroll
-    for (int i = 0; i < kChunkRounds; ++i) {
-        const int64_t g = gs + (int64_t)i * kWave + lane;
-        const int64_t gc = g < ge ? g : ge - 1;
-        oa[i] = offs[gc];
-        ob[i] = offs[gc + 1];
+        for (int k = 0; k < kHistBatch; ++k) {
+            const int64_t g = gs + (int64_t)(i0 + k) * kWave + lane;
+            o[k] = offs[g < ge ? g : ge];
+        }
+        const int64_t gt = gs + (int64_t)(i0 + kHistBatch) * kWave;
+        const int64_t tail = offs[gt < ge ? gt : ge];
+        int Ls[kHistBatch];
+#pragma unroll
+        for (int k = 0; k < kHistBatch; ++k) {
+            const int64_t g = gs + (int64_t)(i0 + k) * kWave + lane;
+            const int64_t after = k + 1 < kHistBatch ? lane0_of(o[k + 1]) : tail;
+            const int64_t o1 = from_next_lane64(after, o[k]);
+            Ls[k] = g < ge ? word_len_o(o[k], o1, first, n_bytes, max_len, bad) : -1;
+            if (g < ge) len8[g] = (uint8_t)(Ls[k] >= 0 ? Ls[k] : 0xFF);
+        }
+#pragma unroll
+        for (int k = 0; k < kHistBatch; ++k)
+            if (Ls[k] >= 0) atomicAdd(&hist[wv][Ls[k]], 1);
     }
-    int Ls[kChunkRounds];
-#pragma unroll
-    for (int i = 0; i < kChunkRounds; ++i) {
-        const int64_t g = gs + (int64_t)i * kWave + lane;
-        Ls[i] = g < ge ? word_len_o(oa[i], ob[i], first, n_bytes, max_len, bad) : -1;
-    }
-#pragma unroll
-    for (int i = 0; i < kChunkRounds; ++i)
-        if (Ls[i] >= 0) atomicAdd(&hist[wv][Ls[i]], 1);
     if (bad) set_status(J, bad);
     __builtin_amdgcn_wave_barrier();
     const gptr<int32_t> ch = gp(J->chunk_hist);
@@ -270,27 +298,36 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ J) {
     // bits that tell lengths 0..max_len and "no word" (all ones) apart
     const int nbits = 32 - __builtin_clz((unsigned)ml1);
     const int none = (1 << nbits) - 1;
-    uint32_t bad = 0, err = 0;
-    for (int i0 = 0; i0 < kChunkRounds; i0 += kScatterBatch) {
+    uint32_t err = 0;
+    const gptr<const uint8_t> len8 = gp(J->len8);
+    // the first offset of the batch's next word: the chunk's first offset,
+    // then the running sum of the lengths (a malformed word counts as empty:
+    // the call has failed, and the range checks below keep every read in
+    // bounds)
+    int64_t run_off = offs[gs];
+    const int rounds = (int)((ge - gs + kWave - 1) / kWave);       // uniform
+    for (int i0 = 0; i0 < rounds; i0 += kScatterBatch) {
         // 1. lengths (and for short words the bytes) of the batch's words
         int Ls[kScatterBatch];
-        int64_t o0[kScatterBatch], o1[kScatterBatch];
+        int64_t o0[kScatterBatch];
         uint32_t q[kScatterBatch][4];
         int shs[kScatterBatch];
         bool qok[kScatterBatch];
-        // loads at in-range indices (a chunk holds at least one word), no
-        // branch around them, so they are all in flight before the first is used
+        uint32_t lb[kScatterBatch];
 #pragma unroll
         for (int k = 0; k < kScatterBatch; ++k) {
             const int64_t g = gs + (int64_t)(i0 + k) * kWave + lane;
-            const int64_t gc = g < ge ? g : ge - 1;
-            o0[k] = offs[gc];
-            o1[k] = offs[gc + 1];
+            lb[k] = g < ge ? (uint32_t)len8[g] : 0xFFu;
         }
 #pragma unroll
         for (int k = 0; k < kScatterBatch; ++k) {
-            const int64_t g = gs + (int64_t)(i0 + k) * kWave + lane;
-            Ls[k] = g < ge ? word_len_o(o0[k], o1[k], first, n_bytes, max_len, bad) : -1;
+            const int L = lb[k] == 0xFFu ? -1 : (int)lb[k];
+            const int v = L > 0 ? L : 0;
+            const int incl = wave_incl_scan(v, lane);
+            o0[k] = run_off + (incl - v);
+            run_off += __builtin_amdgcn_readlane(incl, kWave - 1);
+            // the rebuilt range must lie in the readable bytes
+            Ls[k] = (L >= 0 && o0[k] >= first && o0[k] + L <= n_bytes) ? L : -1;
             qok[k] = false;
             shs[k] = 0;
         }
@@ -352,7 +389,6 @@ __global__ __launch_bounds__(256) void k_scatter(const Job* __restrict__ J) {
             __builtin_amdgcn_wave_barrier();
         }
     }
-    (void)bad;                                         // reported by the histogram pass
     if (err) set_status(J, err);
 }
 
