@@ -66,7 +66,7 @@ def ce_cost(D, L, in_lds):
 SORT_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TOK_SOURCES = ("paper_1407_6603_amd/csrc/k_tokenize.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TRAFFIC = {
-    "k_bucket_lds<2, 1024, 16384>": {"read": 66702384, "write": 22090288,
+    "k_bucket_lds<2, 1024, 16320>": {"read": 66702384, "write": 22090288,
                                      "files": SORT_SOURCES, "sources": "e8a357db5266dc54"},
     "k_bucket_lds<3, 1024, 8192>": {"read": 38602015, "write": 12720800,
                                     "files": SORT_SOURCES, "sources": "e8a357db5266dc54"},
@@ -122,7 +122,7 @@ def lds_caps_for(D):
     """Capacities of the in-LDS size classes for record width D (empty: none)."""
     if not 2 <= D <= LDS_MAX_D:
         return []
-    top = 16384 if D <= 2 else 12288 if D == 3 else 9216 if D == 4 else 7168
+    top = 16320 if D <= 2 else 12288 if D == 3 else 9216 if D == 4 else 7168
     caps = [1024 << c for c in range(4)] + [top]
     return [c for c in caps if D * 4 * c <= LDS_BYTES]
 

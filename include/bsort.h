@@ -188,7 +188,7 @@ bsort_status bsort_sort_batch(const bsort_batch *b, int32_t *perm, const bsort_t
  * one "lds_d<D>_<C>" launch per in-LDS size class of capacity C words for
  * D = 2 .. min(9, ceil(max_len/4)+1) (sub-arrays sorted whole in LDS; C =
  * 1024, 2048, 4096, 8192 where D*4*C <= 144 KiB, and a largest class of
- * 16384, 12288, 9216 or 7168 words for D = 2, 3, 4, 5), and "merge_split"
+ * 16320, 12288, 9216 or 7168 words for D = 2, 3, 4, 5), and "merge_split"
  * (sub-arrays larger than LDS: their chunks sorted in LDS, then one launch
  * that runs every merge-split phase of every such sub-array).
  * bsort_stage_count(max_len) is their number and bsort_stage_name(max_len, i)

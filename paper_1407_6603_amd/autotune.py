@@ -151,7 +151,7 @@ def workload_inputs(name: str, workers: int = 8):
     before the GPU is opened when workers > 1."""
     import wordgen
     if name == "batch4096":
-        return wordgen.batch(workers=workers), 12, "lds_d2_16384"
+        return wordgen.batch(workers=workers), 12, "lds_d2_16320"
     if name == "large4x1M":
         lists = [wordgen.serve_request(10_000 + i, 1_000_000) for i in range(4)]
         return wordgen.Batch.concat(lists), 32, "merge_split"

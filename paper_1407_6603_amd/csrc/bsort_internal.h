@@ -67,11 +67,15 @@ enum : uint32_t {
 // In-LDS sub-arrays: one workgroup holds a whole sub-array of up to
 // lds_cap(c, D) words in LDS (D dwords per word, at most 144 KiB) and sorts
 // it there.  Size classes c = 0..4; the largest class is sized per width D.
+// The largest two-dword class holds 16,320 words (255 rows of 64): its two
+// dword planes then lie 255 x 256 bytes apart, within reach of one
+// ds_read2st64_b32 / ds_write2st64_b32, so a whole record moves in one LDS
+// instruction (at 16,384 words the second plane is one step too far).
 constexpr int kLdsClasses = 5;
 constexpr int kLdsMaxD = 9;
 constexpr int kLdsBytes = 144 * 1024;
 __host__ __device__ constexpr int lds_cap(int c, int D) {
-    return c < 4 ? (1024 << c) : (D <= 2 ? 16384 : D == 3 ? 12288 : D == 4 ? 9216 : 7168);
+    return c < 4 ? (1024 << c) : (D <= 2 ? 16320 : D == 3 ? 12288 : D == 4 ? 9216 : 7168);
 }
 __host__ __device__ constexpr bool lds_fits(int D, int c) {
     return D >= 2 && D <= kLdsMaxD && D * 4 * lds_cap(c, D) <= kLdsBytes;

@@ -686,7 +686,7 @@ __device__ __forceinline__ int wave_count_before(const uint32_t* lds, int cap, i
 }
 
 // per-phase window table in LDS (merge_win_words ints), owned by the kernel
-constexpr int kMaxPairs = 64;                              // 16384 / 128 / 2
+constexpr int kMaxPairs = 64;                              // 16320 / 128 / 2, rounded up
 constexpr int kMergeWinWords = 4 * kMaxPairs + 1;
 
 // WIN: trim each pair to its changing window first (two ballot searches and

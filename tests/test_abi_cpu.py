@@ -149,9 +149,9 @@ for ml in (0, 4, 12, 20, 64, 65):
     got = {int(l.split()[0]): l.split()[1:] for l in out.splitlines()}
     assert got[0] == ["bucketize", "pack", "merge_split"]
     assert got[4] == ["bucketize", "pack", "tiles_d2", "lds_d2_1024", "lds_d2_2048",
-                      "lds_d2_4096", "lds_d2_8192", "lds_d2_16384", "merge_split"]
+                      "lds_d2_4096", "lds_d2_8192", "lds_d2_16320", "merge_split"]
     lds12 = [n for n in got[12] if n.startswith("lds_")]
-    assert lds12 == ["lds_d2_1024", "lds_d2_2048", "lds_d2_4096", "lds_d2_8192", "lds_d2_16384",
+    assert lds12 == ["lds_d2_1024", "lds_d2_2048", "lds_d2_4096", "lds_d2_8192", "lds_d2_16320",
                      "lds_d3_1024", "lds_d3_2048", "lds_d3_4096", "lds_d3_8192", "lds_d3_12288",
                      "lds_d4_1024", "lds_d4_2048", "lds_d4_4096", "lds_d4_8192", "lds_d4_9216"]
     assert [n for n in got[20] if n.startswith("lds_d5")] == \

@@ -262,7 +262,7 @@ def test_zero_one_merge_seams(bs, ws, T):
             p = rng.random()
             seqs.append((rng.random(n) < p).astype(np.int8))
     # past the largest in-LDS sub-array: tiles merged phase by phase through HBM
-    for n in (16385, 16384 + 3 * T + 1, 20000):
+    for n in (16321, 16320 + 3 * T + 1, 20000):
         for _ in range(3):
             p = rng.random()
             seqs.append((rng.random(n) < p).astype(np.int8))
@@ -274,7 +274,7 @@ def test_zero_one_merge_seams(bs, ws, T):
 def lds_caps(D):
     """In-LDS size-class capacities for record width D (largest class per
     width within 144 KiB of LDS; widths 6-9 have the classes up to 4,096)."""
-    top = {2: 16384, 3: 12288, 4: 9216, 5: 7168}.get(D, 8192)
+    top = {2: 16320, 3: 12288, 4: 9216, 5: 7168}.get(D, 8192)
     return [c for c in (1024, 2048, 4096, 8192, top) if D * 4 * c <= 144 * 1024]
 
 
@@ -343,7 +343,7 @@ def test_one_two_byte_words_in_every_class(bs, ws, alphabet):
     HBM, in the two-dword form)."""
     rng = np.random.default_rng(12)
     lists = []
-    for cap in lds_caps(2) + [16384 + 129]:
+    for cap in lds_caps(2) + [16320 + 129]:
         for L in (1, 2):
             for n in (cap - 1, cap // 2 + 3):
                 if alphabet is None:
@@ -372,7 +372,7 @@ def test_three_four_byte_words_in_every_class(bs, ws, alphabet):
     past the largest (merged through HBM)."""
     rng = np.random.default_rng(34)
     lists = []
-    for cap in lds_caps(2) + [16384 + 129]:
+    for cap in lds_caps(2) + [16320 + 129]:
         for L in (3, 4):
             for n in (cap - 1, cap // 2 + 3, 1024):
                 if alphabet is None:
