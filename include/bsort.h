@@ -34,7 +34,8 @@
  *     Scratch space is a caller-allocated workspace of at least
  *     bsort_workspace_bytes(...) bytes, 256-byte aligned.  Calls that run
  *     concurrently must use distinct workspaces.
- *   - Objects the library owns: plans (bsort_plan_create .. destroy), and,
+ *   - Objects the library owns: plans (bsort_plan_create .. destroy, each
+ *     with its own streams for the capture), and,
  *     per device, up to four pools of three HIP streams (default priority)
  *     with their fork/join events.  A batch sort that fans its in-LDS stages
  *     out (the default; see bsort_sort_batch_staged) takes the pool of its
@@ -310,8 +311,9 @@ bsort_status bsort_oets_buckets(const bsort_words *w, const bsort_buckets *b, in
  * graph for batches within the given capacity, then replayed by
  * bsort_plan_execute with one graph launch (plus one small launch that
  * passes the batch's pointers and sizes).  The plan owns a small device
- * buffer and the graph; the workspace still comes from the caller and must
- * hold bsort_plan_workspace_bytes(plan) bytes.
+ * buffer, the graph, and three HIP streams (default priority) with their
+ * events that only its capture uses; the workspace still comes from the
+ * caller and must hold bsort_plan_workspace_bytes(plan) bytes.
  */
 typedef struct bsort_plan bsort_plan;
 bsort_status bsort_plan_create(bsort_plan **plan, int64_t cap_words, int32_t cap_requests,

@@ -259,6 +259,8 @@ bsort_status plain_form(const bsort_batch* b, int32_t* perm, const bsort_tuning*
 
 }  // namespace
 
+struct FanPool;
+
 struct bsort_plan {
     int64_t cap_words;
     int64_t cap_req;
@@ -269,6 +271,7 @@ struct bsort_plan {
     Bounds bd;
     Job* job_dev;
     hipGraphExec_t exec;
+    FanPool* fan;            // the plan's own library streams and events (captured into its graph)
 };
 
 extern "C" {
@@ -352,7 +355,7 @@ bsort_status bsort_bucketize(const bsort_words* w, const bsort_buckets* b, void*
 }
 
 static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
-                               void* const* ev);
+                               void* const* ev, FanPool* own);
 
 bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, int32_t* perm,
                                 const bsort_tuning* t, void* ws, size_t ws_bytes,
@@ -377,7 +380,7 @@ bsort_status bsort_sort_buckets(const bsort_words* w, const bsort_buckets* b, in
     j.order = b->order;
     j.perm = perm;
     HIP_TRY(launch_set_job(j, jd, s));
-    HIP_TRY(enqueue_sort(jd, bd, s, false, nullptr));
+    HIP_TRY(enqueue_sort(jd, bd, s, false, nullptr, nullptr));
     return BSORT_OK;
 }
 
@@ -531,16 +534,17 @@ static hipError_t fan_init(FanPool& f) {
     return e;
 }
 
-// set up the pool a stream will use (allocations are not allowed while a
-// stream is being captured, so plans call this before capturing)
-static hipError_t fan_prepare(hipStream_t s) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    FanPool& f = g_fan[dev][fan_pool_for(dev, s)];
-    std::lock_guard<std::mutex> lock(f.mu);
-    return fan_init(f);
+// a pool's streams and events (a plan's own pool, when the plan is destroyed)
+static void fan_destroy(FanPool& f) {
+    if (!f.ready) return;
+    for (int k = 0; k < kFan - 1; ++k) {
+        if (f.aux[k]) (void)hipStreamDestroy(f.aux[k]);
+        if (f.join[k]) (void)hipEventDestroy(f.join[k]);
+    }
+    if (f.fork) (void)hipEventDestroy(f.fork);
+    if (f.prep_fork) (void)hipEventDestroy(f.prep_fork);
+    if (f.prep_join) (void)hipEventDestroy(f.prep_join);
+    f.ready = false;
 }
 
 enum StageKind { kStageTiles, kStageLds, kStageMerge };
@@ -580,8 +584,9 @@ static hipError_t run_stage(const StageRef& st, const Job* J, const Bounds& b, h
 // before and after the stage on the stream that runs it.  Nothing is read
 // back: every launch size is fixed on the host, and the merge-split phases run
 // in one launch that finds its work on the device.
+// own: the pool to fan out over (a plan's own); else the pool of the caller's stream
 static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, bool bucketize,
-                               void* const* ev) {
+                               void* const* ev, FanPool* own) {
     auto rec = [&](int i, int end, hipStream_t x) -> hipError_t {
         return ev && ev[2 * i + end] ? hipEventRecord((hipEvent_t)ev[2 * i + end], x) : hipSuccess;
     };
@@ -592,7 +597,7 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     int dev = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    FanPool& f = g_fan[dev][fan ? fan_pool_for(dev, s) : 0];
+    FanPool& f = own ? *own : g_fan[dev][fan ? fan_pool_for(dev, s) : 0];
     std::unique_lock<std::mutex> lock(f.mu, std::defer_lock);
     if (fan) {
         lock.lock();
@@ -681,7 +686,7 @@ static bsort_status sort_batch_impl(const bsort_batch* b, int32_t* perm, const b
     Job* jd = (Job*)((char*)ws + L.job);
     Job j = batch_job(L, (char*)ws, bd, b, total, perm);
     HIP_TRY(launch_set_job(j, jd, s));
-    HIP_TRY(enqueue_sort(jd, bd, s, true, events));
+    HIP_TRY(enqueue_sort(jd, bd, s, true, events, nullptr));
     return BSORT_OK;
 }
 
@@ -723,19 +728,26 @@ bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap
     p->bd.fused_pack = 1;
     p->job_dev = nullptr;
     p->exec = nullptr;
+    // the plan's own library streams and events: a capture never shares
+    // streams with eager calls (or with other plans) while it records
+    p->fan = new (std::nothrow) FanPool();
+    if (!p->fan) {
+        delete p;
+        return fail(BSORT_E_NO_MEMORY, "plan allocation");
+    }
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipError_t e = hipMalloc((void**)&p->job_dev, sizeof(Job));
     if (e != hipSuccess) {
+        delete p->fan;
         delete p;
         return fail(BSORT_E_NO_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
-    e = hipSuccess;
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e == hipSuccess) e = fan_prepare(cs);
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = fan_init(*p->fan);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = enqueue_sort(p->job_dev, p->bd, cs, true, nullptr);
+        hipError_t e1 = enqueue_sort(p->job_dev, p->bd, cs, true, nullptr, p->fan);
         e = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = e1;
     }
@@ -744,6 +756,8 @@ bsort_status bsort_plan_create(bsort_plan** plan, int64_t cap_words, int32_t cap
     if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         (void)hipFree(p->job_dev);
+        fan_destroy(*p->fan);
+        delete p->fan;
         delete p;
         return fail(BSORT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     }
@@ -775,6 +789,10 @@ void bsort_plan_destroy(bsort_plan* p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->job_dev) (void)hipFree(p->job_dev);
+    if (p->fan) {
+        fan_destroy(*p->fan);
+        delete p->fan;
+    }
     delete p;
 }
 
@@ -847,7 +865,7 @@ bsort_status bsort_sort_batch_static(const bsort_batch* b, int32_t* perm, const 
         Job* jd = (Job*)((char*)ws + L.job);
         Job j = batch_job(L, (char*)ws, bd, b, total, perm);
         HIP_TRY(launch_set_job(j, jd, s));
-        HIP_TRY(enqueue_sort(jd, bd, s, true, nullptr));
+        HIP_TRY(enqueue_sort(jd, bd, s, true, nullptr, nullptr));
     }
     if (status) {
         k_status_out<<<1, 64, 0, s>>>(
