@@ -66,16 +66,16 @@ def ce_cost(D, L, in_lds):
 SORT_SOURCES = ("paper_1407_6603_amd/csrc/k_oets.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TOK_SOURCES = ("paper_1407_6603_amd/csrc/k_tokenize.hip", "paper_1407_6603_amd/csrc/bsort_internal.h")
 TRAFFIC = {
-    "k_bucket_lds<2, 1024, 16320>": {"read": 66702384, "write": 22090288,
-                                     "files": SORT_SOURCES, "sources": "e8a357db5266dc54"},
-    "k_bucket_lds<3, 1024, 8192>": {"read": 38602015, "write": 12720800,
-                                    "files": SORT_SOURCES, "sources": "e8a357db5266dc54"},
-    "k_tok_count": {"read": 189666685, "write": 746000,
-                    "files": TOK_SOURCES, "sources": "68fd582c5aaea8f0"},
-    "k_tok_scan": {"read": 110204, "write": 183712,
-                   "files": TOK_SOURCES, "sources": "68fd582c5aaea8f0"},
-    "k_tok_write": {"read": 191130437, "write": 403942352,
-                    "files": TOK_SOURCES, "sources": "68fd582c5aaea8f0"},
+    "k_bucket_lds<2, 1024, 16320>": {"read": 66795065, "write": 22089840,
+                                     "files": SORT_SOURCES, "sources": "803a2ebbb5cc19a2"},
+    "k_bucket_lds<3, 1024, 8192>": {"read": 38552314, "write": 12720619,
+                                    "files": SORT_SOURCES, "sources": "803a2ebbb5cc19a2"},
+    "k_tok_count": {"read": 189750924, "write": 744432,
+                    "files": TOK_SOURCES, "sources": "3c0108557ac3244c"},
+    "k_tok_scan": {"read": 110205, "write": 183712,
+                  "files": TOK_SOURCES, "sources": "3c0108557ac3244c"},
+    "k_tok_write": {"read": 191134246, "write": 403949504,
+                    "files": TOK_SOURCES, "sources": "3c0108557ac3244c"},
 }
 
 
