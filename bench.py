@@ -70,12 +70,6 @@ TRAFFIC = {
                                      "files": SORT_SOURCES, "sources": "803a2ebbb5cc19a2"},
     "k_bucket_lds<3, 1024, 8192>": {"read": 38552314, "write": 12720619,
                                     "files": SORT_SOURCES, "sources": "803a2ebbb5cc19a2"},
-    "k_tok_count": {"read": 189750924, "write": 744432,
-                    "files": TOK_SOURCES, "sources": "3c0108557ac3244c"},
-    "k_tok_scan": {"read": 110205, "write": 183712,
-                  "files": TOK_SOURCES, "sources": "3c0108557ac3244c"},
-    "k_tok_write": {"read": 191134246, "write": 403949504,
-                    "files": TOK_SOURCES, "sources": "3c0108557ac3244c"},
 }
 
 

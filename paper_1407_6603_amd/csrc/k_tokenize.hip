@@ -7,18 +7,25 @@
 // int64 offsets, word i = out[offsets[i] .. offsets[i+1]).
 //
 // A stream compaction bound by HBM bandwidth, over tiles of 16 KiB of text
-// (one workgroup of 256 threads, 64 consecutive bytes per thread read with
-// four 16-byte loads; a thread's letters form one 64-bit mask):
+// (one workgroup of 256 threads, four 16-byte loads per thread):
 //   count   per tile: letters, word starts (a letter whose previous byte is
 //           not one), and the letters before its first and after its last
-//           word start;
+//           word start (from the positions of its first non-letter, last
+//           letter and last start, so its loads are coalesced);
 //   scan    one workgroup: exclusive prefix of letters and words over the
 //           tiles, the totals, the closing offset, and the longest word
 //           that reaches past a tile's end (tiles joined in text order);
-//   write   per tile again: a block scan gives each thread its letter and
-//           word ranks; letters and word starts are compacted through LDS
-//           and stored in order (letters as aligned dwords), and the
+//   write   per tile again, 64 consecutive bytes per thread (its letters
+//           form one 64-bit mask): a block scan gives each thread its letter
+//           and word ranks; letters and word starts are compacted through
+//           LDS and stored in order (letters as aligned dwords), and the
 //           longest word inside the tile is folded into the result.
+// Three passes read the text twice, but no workgroup waits on another.  A
+// single pass (each tile folding the counts its predecessors publish) has
+// to poll across the eight XCDs, whose L2 caches are not coherent with each
+// other: every poll goes past L2 and queues behind the text stream, and
+// that costs more than the second read of a text that the 256 MB
+// last-level cache largely still holds.
 // The text pointer may have any alignment: tiles are laid over the text
 // rounded down to 16 bytes, interior 16-byte chunks are read with one load,
 // and chunks at either end byte by byte inside the text only.
@@ -34,8 +41,15 @@ constexpr int kTokLoads = 4;                           // loads per thread
 constexpr int kTokSpan = kTokBytes * kTokLoads;        // 64 consecutive text bytes per thread
 constexpr int kTokTile = kTokThreads * kTokSpan;       // 16 KiB of text per workgroup
 constexpr int kTokWaves = kTokThreads / kWave;
+// LDS staging of a tile in the write pass: its L letters from byte skew
+// (0..3) on, then its W 16-bit word starts from the next dword on.  A word
+// has a letter (W <= L), and word starts inside a tile are separated by
+// non-letters (W - 1 <= 16384 - L), so L + 2W is largest at L = 8193,
+// W = 8192 (24,577 bytes) and the starts end by byte 24,584.  Sized for that
+// rather than for 16 KiB of each, so that six workgroups fit in a compute
+// unit's LDS, not four.
+constexpr int kTokStageBytes = 24584;
 constexpr int kTokScanThreads = 1024;
-constexpr int kTokCountTiles = 1;                      // tiles per counting workgroup
 
 inline size_t tok_align(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -158,15 +172,7 @@ __device__ __forceinline__ Run<T> wave_join(Run<T> r, int lane) {
     return r;
 }
 
-// wave-wide min and max
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        const uint32_t o = __shfl_xor(v, d, kWave);
-        v = o < v ? o : v;
-    }
-    return v;
-}
+// wave-wide max
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
@@ -178,62 +184,85 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 
 // tile_counts[i] = packed counts of tile i; tile_ends[i] = (letters of the
 // tile after its last word start << 16) | letters before its first one
-// (both 0 when the tile has no word start).  Loads past the last tile read
-// nothing (positions beyond the text).
+// (both 0 when the tile has no word start).
+//
+// Counting needs no text order inside the tile, so the loads are laid out
+// for coalescing: load k of thread t reads bytes k * 4096 + 16t .. +15 of
+// the tile (a wave's load is 1 KiB of consecutive text).  A 16-byte chunk's
+// previous byte is the last byte of the previous lane's chunk, or, for lane
+// 0, read from memory.  The two run lengths come from positions:
+//   letters before the first word start: if the byte before the tile is a
+//     letter, the tile's leading letters continue a word and end at its
+//     first non-letter, so they number that non-letter's position; else 0;
+//   letters from the last word start on: the last start opens the tile's
+//     last run of letters, so last letter's position + 1 - last start's.
 __global__ __launch_bounds__(kTokThreads) void k_tok_count(TokText t, int64_t ntiles,
                                                            uint32_t* __restrict__ tile_counts,
                                                            uint32_t* __restrict__ tile_ends) {
-    __shared__ uint32_t wsum[kTokWaves], wfirst[kTokWaves], wlast[kTokWaves];
+    constexpr int kRow = kTokThreads * kTokBytes;      // 4 KiB of text per load round
+    __shared__ uint32_t wsum[kTokWaves], wnon[kTokWaves], wlet[kTokWaves], wst[kTokWaves];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // kTokCountTiles consecutive tiles per workgroup, all loads issued first
-    uint32_t d[kTokCountTiles][kTokLoads][4];
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kTokTile;
+    uint32_t d[kTokLoads][4];
 #pragma unroll
-    for (int q = 0; q < kTokCountTiles; ++q)
-        load_span(t, ((int64_t)blockIdx.x * kTokCountTiles + q) * kTokTile + (int64_t)tid * kTokSpan,
-                  d[q]);
+    for (int k = 0; k < kTokLoads; ++k) load_chunk(t, base + k * kRow + kTokBytes * tid, d[k]);
+    // lane 0: the byte before each of its chunks
+    uint32_t before0 = 0;
+    if (lane == 0) {
+        const gptr<const uint8_t> tb = gp(t.base);
 #pragma unroll
-    for (int q = 0; q < kTokCountTiles; ++q) {
-        const int64_t tile = (int64_t)blockIdx.x * kTokCountTiles + q;
-        if (tile >= ntiles) break;                     // uniform
-        const int64_t c = tile * kTokTile + (int64_t)tid * kTokSpan;
-        uint64_t M, S;
-        span_masks(t, c, d[q], M, S);
-        const uint32_t v = packed_counts(M, S);
-        const uint32_t incl = wave_incl_scan(v, lane);
-        if (lane == 63) wsum[wv] = incl;
-        __syncthreads();
-        uint32_t ll = (incl - v) & 0xFFFFu, total = 0;    // letters of the tile before this thread
+        for (int k = 0; k < kTokLoads; ++k) {
+            const int64_t p = base + k * kRow + kTokBytes * tid - 1;
+            if (p >= t.head && p < t.N && is_letter(tb[p])) before0 |= 1u << k;
+        }
+    }
+    uint32_t sum = 0;                                  // (word starts << 16) | letters
+    uint32_t non = 0xFFFFFFFFu, let = 0, st = 0;       // first non-letter, last letter + 1, last start + 1
+#pragma unroll
+    for (int k = 0; k < kTokLoads; ++k) {
+        const uint32_t m = byte_mask(letter_bits(d[k][0]), letter_bits(d[k][1])) |
+                           byte_mask(letter_bits(d[k][2]), letter_bits(d[k][3])) << 8;
+        const uint32_t up = (uint32_t)__shfl_up((int)(m >> 15), 1, kWave);
+        const uint32_t prev = lane == 0 ? (before0 >> k) & 1u : up & 1u;
+        const uint32_t sm = m & ~((m << 1) | prev) & 0xFFFFu;
+        sum += ((uint32_t)__popc(sm) << 16) | (uint32_t)__popc(m);
+        const uint32_t pos = (uint32_t)(k * kRow + kTokBytes * tid);
+        const uint32_t nm = ~m & 0xFFFFu;
+        if (nm) non = min(non, pos + (uint32_t)__builtin_ctz(nm));
+        if (m) let = max(let, pos + 32u - (uint32_t)__builtin_clz(m));
+        if (sm) st = max(st, pos + 32u - (uint32_t)__builtin_clz(sm));
+    }
+    // wave sums and extremes, then the tile's
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += (uint32_t)__shfl_xor((int)sum, o, kWave);
+        non = min(non, (uint32_t)__shfl_xor((int)non, o, kWave));
+        let = max(let, (uint32_t)__shfl_xor((int)let, o, kWave));
+        st = max(st, (uint32_t)__shfl_xor((int)st, o, kWave));
+    }
+    if (lane == 0) {
+        wsum[wv] = sum;
+        wnon[wv] = non;
+        wlet[wv] = let;
+        wst[wv] = st;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t total = 0, fn = 0xFFFFFFFFu, ll = 0, ls = 0;
 #pragma unroll
         for (int w = 0; w < kTokWaves; ++w) {
-            ll += w < wv ? (wsum[w] & 0xFFFFu) : 0u;
             total += wsum[w];
+            fn = min(fn, wnon[w]);
+            ll = max(ll, wlet[w]);
+            ls = max(ls, wst[w]);
         }
-        // letter ranks of this thread's first and last word start
-        uint32_t first = 0xFFFFFFFFu, last = 0;
-        if (S) {
-            first = ll + (uint32_t)__popcll(M & ((1ull << __builtin_ctzll(S)) - 1ull));
-            last = ll + (uint32_t)__popcll(M & ((1ull << (63 - __builtin_clzll(S))) - 1ull));
-        }
-        first = wave_min(first);
-        last = wave_max(last);
-        if (lane == 0) {
-            wfirst[wv] = first;
-            wlast[wv] = last;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t f = 0xFFFFFFFFu, l = 0;
-#pragma unroll
-            for (int w = 0; w < kTokWaves; ++w) {
-                f = wfirst[w] < f ? wfirst[w] : f;
-                l = wlast[w] > l ? wlast[w] : l;
-            }
-            const uint32_t nl = total & 0xFFFFu;
-            const bool any = (total >> 16) != 0;
-            gp(tile_counts)[tile] = total;
-            gp(tile_ends)[tile] = any ? ((nl - l) << 16) | f : 0u;
-        }
-        __syncthreads();                               // wsum, wfirst, wlast reused
+        const int64_t p = base - 1;
+        const bool cont = p >= t.head && p < t.N && is_letter(gp(t.base)[p]);
+        const uint32_t pre = cont ? (fn == 0xFFFFFFFFu ? (uint32_t)kTokTile : fn) : 0u;
+        const bool any = (total >> 16) != 0;
+        gp(tile_counts)[tile] = total;
+        gp(tile_ends)[tile] = any ? ((ll - (ls - 1)) << 16) | pre : 0u;
     }
 }
 
@@ -324,12 +353,12 @@ __global__ __launch_bounds__(kTokThreads) void k_tok_write(TokText t,
                                                            int64_t cap_words,
                                                            int64_t* __restrict__ result) {
     // the tile's letters, placed at (global letter address mod 4) + rank so
-    // that aligned global dwords are aligned LDS dwords, and its word starts
-    // as letter ranks within the tile, both stored out in order at the end
-    // (+ one dword per lane past the end: every byte of a span is stored,
-    // non-letters to their lane's spare dword, so the staging has no branch)
-    __shared__ uint32_t stage32[kTokTile / 4 + 2 + kWave];
-    __shared__ uint16_t wstart[kTokTile / 2];
+    // that aligned global dwords are aligned LDS dwords, then its word starts
+    // as 16-bit letter ranks within the tile from the next dword on, both
+    // stored out in order at the end (+ one dword per lane past the end:
+    // every byte of a span is stored, non-letters to their lane's spare
+    // dword, so the staging has no branch)
+    __shared__ uint32_t stage32[kTokStageBytes / 4 + kWave];
     __shared__ uint32_t wmax[kTokWaves];
     __shared__ uint32_t wsum[kTokWaves];
     uint8_t* stage = (uint8_t*)stage32;
@@ -354,9 +383,11 @@ __global__ __launch_bounds__(kTokThreads) void k_tok_write(TokText t,
         total += wsum[w];
     }
     const int ll = (int)(before & 0xFFFFu);           // letters of the tile before this thread
+    const int nl = (int)(total & 0xFFFFu);
+    uint16_t* wstart = (uint16_t*)(stage + ((skew + nl + 3) & ~3));
     // letters, compacted in order into LDS
     int pos = skew + ll;
-    const int spare = 4 * (kTokTile / 4 + 2 + lane);
+    const int spare = kTokStageBytes + 4 * lane;
 #pragma unroll
     for (int k = 0; k < kTokLoads; ++k)
 #pragma unroll
@@ -391,7 +422,6 @@ __global__ __launch_bounds__(kTokThreads) void k_tok_write(TokText t,
     if (lane == 0) wmax[wv] = inner;
     // letters [lb, lb + nl): the partial dwords at both ends byte by byte,
     // the rest as aligned dwords
-    const int nl = (int)(total & 0xFFFFu);
     const gptr<uint8_t> o = gp(out) + lb;             // o - skew is 4-byte aligned
     const int first = skew ? 4 - skew : 0;             // bytes before the first aligned dword
     if (tid < first && tid < nl) o[tid] = stage[skew + tid];
@@ -439,8 +469,7 @@ hipError_t launch_tokenize(const uint8_t* text, int64_t n_bytes, uint8_t* out, i
     w += tok_align(sizeof(uint32_t) * (size_t)nt);
     int64_t* tb = (int64_t*)w;
     if (nt > 0)
-        k_tok_count<<<(unsigned)((nt + kTokCountTiles - 1) / kTokCountTiles), kTokThreads, 0, s>>>(
-            t, nt, tc, te);
+        k_tok_count<<<(unsigned)nt, kTokThreads, 0, s>>>(t, nt, tc, te);
     k_tok_scan<<<1, kTokScanThreads, 0, s>>>(tc, te, nt, tb, offsets, cap_words, result);
     if (nt > 0)
         k_tok_write<<<(unsigned)nt, kTokThreads, 0, s>>>(t, tb, out, offsets, cap_words, result);

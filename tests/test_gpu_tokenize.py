@@ -1,8 +1,9 @@
 """GPU pre-processing (raw text -> words) vs the CPU oracle, through the C ABI.
 
 Byte and index work: every comparison is bit-exact.  Sizes span one and many
-4096-byte tiles, ragged tails, every alignment of the text pointer, and a
-32 MiB text of random bytes.
+16 KiB tiles, ragged tails, every alignment of the text pointer, words
+spanning whole tiles, tiles that fill the write pass's staging, and texts of
+32 and 96 MiB.
 """
 import numpy as np
 import pytest
@@ -163,3 +164,64 @@ def test_sort_text_word_too_long(bs, ws):
     assert ml == 70
     with pytest.raises(bs.BsortError):
         bs.sort_text(t, ws=ws)
+
+
+TILE = 16384
+
+
+@pytest.mark.parametrize("tiles", [63, 64, 65, 128, 129, 200])
+def test_tile_counts(bs, ws, tiles):
+    """Texts of a few hundred tiles, exact multiples and ragged: every tile's
+    offsets come from the scan of the tiles' counts."""
+    rng = np.random.default_rng(tiles)
+    al = np.frombuffer(b"abcdefgh  ,Q", dtype=np.uint8)
+    for n in (tiles * TILE - 1, tiles * TILE, tiles * TILE + 7):
+        check_against_oracle(bs, ws, al[rng.integers(0, len(al), size=n)], shift=n % 5)
+
+
+def test_words_spanning_whole_tiles(bs, ws):
+    """Letter runs that cover whole tiles (tiles with no word start): the
+    scan must carry the letters after the last word start through them."""
+    rng = np.random.default_rng(11)
+    al = np.frombuffer(b"ab c", dtype=np.uint8)
+    text = al[rng.integers(0, len(al), size=140 * TILE)].copy()
+    for start, length in ((62 * TILE + 100, 3 * TILE), (127 * TILE - 5, TILE + 10),
+                          (130 * TILE, 5 * TILE + 1)):
+        text[start:start + length] = ord("Z")
+        text[start - 1] = ord(" ")
+    check_against_oracle(bs, ws, text)
+    b, o, ml = gpu_tokenize(bs, ws, text)
+    assert ml >= 5 * TILE + 1
+
+
+def test_workspace_reused_across_sizes(bs, ws):
+    """One workspace, calls of falling and rising size back to back on one
+    stream: nothing a call leaves in it reaches the next."""
+    rng = np.random.default_rng(5)
+    al = np.frombuffer(b"xyz w", dtype=np.uint8)
+    for n in (300 * TILE + 3, 2 * TILE, 17, 70 * TILE, 0, 5 * TILE + 1):
+        check_against_oracle(bs, ws, al[rng.integers(0, len(al), size=n)])
+
+
+def test_large_text_with_long_runs(bs, ws):
+    """96 MiB (6,144 tiles, more than the device holds at once) with long
+    runs across tiles placed at random."""
+    rng = np.random.default_rng(96)
+    al = np.frombuffer(b"etaoinshrdlu  ,.Q", dtype=np.uint8)
+    text = al[rng.integers(0, len(al), size=96 << 20)]
+    for start in rng.integers(0, len(text) - 3 * TILE, size=20):
+        text[start:start + int(rng.integers(1, 3 * TILE))] = ord("k")
+    check_against_oracle(bs, ws, text, shift=9)
+
+
+def test_tile_staging_worst_case(bs, ws):
+    """Tiles holding the most letters plus 16-bit word starts the staging can
+    meet: 8,193 letters and 8,192 word starts in each 16 KiB ("aa" then
+    " a" repeated), tile-aligned and shifted; and one-letter words
+    throughout."""
+    tile = b"aa" + b" a" * ((TILE - 2) // 2)
+    assert len(tile) == TILE
+    text = np.frombuffer(tile * 12, dtype=np.uint8)
+    for shift in (0, 1, 5):
+        check_against_oracle(bs, ws, text, shift=shift)
+    check_against_oracle(bs, ws, np.frombuffer(b"a " * (6 * TILE) + b"z", dtype=np.uint8))
