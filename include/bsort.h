@@ -263,7 +263,9 @@ bsort_status bsort_tokenize(const uint8_t *text, int64_t n_bytes, uint8_t *words
  * sub-array per list and run the same odd-even transposition sort and
  * merge-split over the whole list:
  *   BSORT_KEY_BYTES         the word's bytes, zero-padded to width
- *                           (alphabetic order; width >= longest word)
+ *                           (alphabetic order; width >= longest word; a
+ *                           word holding a 0x00 byte ties with itself cut
+ *                           there, since padding is 0x00 too)
  *   BSORT_KEY_LENGTH        one byte holding the length (width 1)
  *   BSORT_KEY_LENGTH_BYTES  the length byte, then the padded bytes (the
  *                           bucketed sort's order; width >= 1 + longest)
