@@ -633,7 +633,15 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     const std::vector<StageRef> stages = sort_stages(b);
     // the tile sorts first on the caller's stream (short; the merge-split
     // waits on them), then the in-LDS classes round-robin on the library
-    // streams, then the merge-split after the tiles on the caller's stream
+    // streams, then the merge-split after the tiles on the caller's stream.
+    // The classes come in (capacity level, record width) order, so plain
+    // round-robin gives each library stream one record width (faster for
+    // eager calls).  A plan's capture turns the assignment one stream
+    // further at each capacity level, so each stream's chain mixes widths
+    // and the chains are of more even length: the runtime replays a graph on
+    // streams of its own, which need not keep one chain per queue, and there
+    // even chains were measured faster.
+    const bool rotate = own != nullptr;
     for (const StageRef& g : stages) {
         if (g.kind != kStageTiles) continue;
         if ((e = rec(g.index, 0, s)) != hipSuccess) return e;
@@ -643,7 +651,9 @@ static hipError_t enqueue_sort(const Job* J, const Bounds& b, hipStream_t s, boo
     int lds_seen = 0;
     for (const StageRef& g : stages) {
         if (g.kind != kStageLds) continue;
-        hipStream_t x = fan ? st[1 + (lds_seen++) % (kFan - 1)] : s;
+        const int rr = rotate ? lds_seen + lds_seen / (kFan - 1) : lds_seen;
+        ++lds_seen;
+        hipStream_t x = fan ? st[1 + rr % (kFan - 1)] : s;
         if ((e = rec(g.index, 0, x)) != hipSuccess) return e;
         if ((e = run_stage(g, J, b, x)) != hipSuccess) return e;
         if ((e = rec(g.index, 1, x)) != hipSuccess) return e;
