@@ -70,6 +70,12 @@ TRAFFIC = {
                                      "files": SORT_SOURCES, "sources": "803a2ebbb5cc19a2"},
     "k_bucket_lds<3, 1024, 8192>": {"read": 38552314, "write": 12720619,
                                     "files": SORT_SOURCES, "sources": "803a2ebbb5cc19a2"},
+    "k_tok_count": {"read": 189711877, "write": 738000,
+                    "files": TOK_SOURCES, "sources": "eb8edcd7ea267f4b"},
+    "k_tok_scan": {"read": 109053, "write": 183712,
+                   "files": TOK_SOURCES, "sources": "eb8edcd7ea267f4b"},
+    "k_tok_write": {"read": 191245979, "write": 404112288,
+                    "files": TOK_SOURCES, "sources": "eb8edcd7ea267f4b"},
 }
 
 
